@@ -1,0 +1,171 @@
+/*
+ * rsfde.h — C ABI of the MI355X (gfx950) solver for the volume-penalized
+ * implicit finite-difference system of the 2-D Riesz space-fractional
+ * diffusion equation, preconditioned by the sine-transform (tau) matrices.
+ *
+ * Paper: X. Huang, H.-W. Sun, "A preconditioner based on sine transform for
+ * two-dimensional Riesz space fractional diffusion equations in convex
+ * domains", arXiv 2102.11576.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: n1 x n2 interior points of the box (x_lo,x_hi) x (y_lo,y_hi),
+ *    h_x = (x_hi-x_lo)/(n1+1), h_y = (y_hi-y_lo)/(n2+1)  (Section 2).
+ *  - Vectors are FP64 device arrays of N = n1*n2 entries in row-major
+ *    [n2][n1] order (x fastest) — the lexicographic ordering of Section 2.
+ *    They are owned by the caller, must not overlap unless stated, and must
+ *    stay valid until the call returns.
+ *  - mask: uint8 device array [n2][n1], 1 = grid point inside the convex
+ *    domain, 0 = penalty region (the paper's Phi_d is diag(1 - mask)).
+ *  - stream: a hipStream_t passed as void* (NULL = the stream given at setup).
+ *    All device work of a call is enqueued on that stream.  Calls that run the
+ *    Krylov solver return after the solve has finished (the host takes the
+ *    convergence decisions); matvec / precond_apply return after enqueueing.
+ *  - Every function returns RSFDE_OK (0) or a negative error code; no C++
+ *    exception crosses the ABI.  Arguments are validated on the host before
+ *    any device work is enqueued.
+ *  - A plan is bound to the device that was current at setup, holds all of
+ *    its workspaces (no allocation after setup), and is not thread-safe.
+ */
+#ifndef RSFDE_H
+#define RSFDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define RSFDE_OK 0
+#define RSFDE_EINVAL (-1)       /* invalid argument (checked before any device work) */
+#define RSFDE_ENOMEM (-2)       /* device or pinned-host allocation failed at setup */
+#define RSFDE_EHIP (-3)         /* a HIP runtime call failed */
+#define RSFDE_ENOTCONV (-4)     /* iteration cap reached; output holds the last iterate */
+#define RSFDE_EBREAKDOWN (-5)   /* Arnoldi breakdown with the true residual above tol */
+#define RSFDE_ENONFINITE (-6)   /* NaN or Inf in the input or in the Krylov recurrence */
+#define RSFDE_EUNSUPPORTED (-7) /* valid but not implemented for this shape / option */
+
+/* precision of the preconditioner apply (the rest of the solve is FP64) */
+#define RSFDE_FP64 0
+#define RSFDE_FP32 1
+#define RSFDE_BF16 2
+
+/* preconditioner */
+#define RSFDE_PRECOND_TAU 0  /* the sine-transform preconditioner P_hat (Section 4.1) */
+#define RSFDE_PRECOND_NONE 1 /* plain GMRES */
+
+/* nonlinear source term f(u) (zero outside the domain, Section 2) */
+#define RSFDE_F_NONE 0     /* f = 0 */
+#define RSFDE_F_LOGISTIC 1 /* f = u (1 - u) */
+#define RSFDE_F_SIN 2      /* f = sin u */
+#define RSFDE_F_CUBIC 3    /* f = u - u^3 */
+
+typedef struct rsfde_plan_s* rsfde_plan;
+
+typedef struct {
+  int32_t n1, n2;           /* interior points in x and y, >= 1 */
+  double x_lo, x_hi;        /* box in x, x_hi > x_lo */
+  double y_lo, y_hi;        /* box in y, y_hi > y_lo */
+} rsfde_grid;
+
+typedef struct {
+  int32_t restart;   /* GMRES restart length, 1 .. max_restart of the plan */
+  int32_t max_iters; /* cap on inner iterations per solve (>= 1) */
+  double tol;        /* stop when ||b - M x||_2 <= tol * ||b||_2 (tol > 0) */
+  int32_t precision; /* RSFDE_FP64 / RSFDE_FP32 / RSFDE_BF16: preconditioner arithmetic */
+  int32_t precond;   /* RSFDE_PRECOND_TAU or RSFDE_PRECOND_NONE */
+} rsfde_solver_opts;
+
+typedef struct {
+  int32_t iters;      /* inner (Arnoldi) iterations used by the solve */
+  int32_t restarts;   /* restart cycles started */
+  int32_t status;     /* same code as the return value */
+  int32_t reserved;
+  double relres;      /* true relative residual ||b - M x|| / ||b|| at exit */
+  double bnorm;       /* ||b||_2 */
+} rsfde_stats;
+
+/*
+ * Create a plan: GL weights (g_form), c_alpha = -1/(2 cos(alpha pi/2)),
+ * c_x = dt kx c_alpha1 / h_x^alpha1 and c_y likewise (Section 2), the Toeplitz
+ * first columns of (G), the circulant-embedding symbols used by the O(N log N)
+ * matrix-vector product, and the tau-matrix eigenvalues diagonalised by the
+ * sine transform (Section 4.1).  Copies the mask (N bytes) into plan memory.
+ *   out         : receives the plan (set to NULL on error)
+ *   grid        : host pointer
+ *   alpha1/2    : fractional orders, 1 < alpha < 2
+ *   kx, ky      : diffusion coefficients, >= 0 (can be changed later)
+ *   mask_dev    : device pointer [n2][n1]
+ *   eta, dt     : penalty parameter > 0 and time step > 0
+ *   max_restart : largest restart the plan will run (1..64; <= 0 means 30)
+ *   stream      : stream for the set-up uploads
+ * The sine-transform preconditioner requires n1+1 and n2+1 to be powers of
+ * two (the FFT lengths 2(n+1)); other sizes support the matrix-vector product
+ * and RSFDE_PRECOND_NONE only.  Sizes up to n = 8191 per direction.
+ * Errors: EINVAL, ENOMEM, EHIP.
+ */
+int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double alpha2,
+                double kx, double ky, const uint8_t* mask_dev, double eta, double dt,
+                int32_t max_restart, void* stream);
+
+/* Change kx, ky (O(1): the symbols and eigenvalues are stored for k = 1 and
+ * scaled at apply time).  Errors: EINVAL. */
+int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky);
+
+/* y = M x with M = I - A + D, A = I (x) A_x + A_y (x) I (matrix_vector,
+ * toeplitz_A): two FFT-convolution passes.  x and y must not overlap.
+ * Errors: EINVAL, EHIP. */
+int rsfde_matvec(rsfde_plan plan, const double* x, double* y, void* stream);
+
+/* z = P_hat^{-1} r (preconditioner): 2-D DST-I, the two eigenvalue scalings
+ * 1/(1 - lx_i - ly_j) and 1/(1 + dt/eta - lx_i - ly_j), inverse 2-D DST-I,
+ * combined by the mask.  precision selects the internal arithmetic (FP64,
+ * FP32; BF16 returns EUNSUPPORTED in this build).  r and z must not overlap.
+ * Errors: EINVAL, EUNSUPPORTED, EHIP. */
+int rsfde_precond_apply(rsfde_plan plan, const double* r, double* z, int32_t precision,
+                        void* stream);
+
+/* One implicit time step (difference_scheme / linearsystem):
+ *   b = u_prev + dt * mask * f(u_prev),  solve M u_next = b
+ * by restarted right-preconditioned flexible GMRES, initial guess
+ * 2 u_prev - u_prev2 (u_prev if u_prev2 is NULL) as in Section 5.
+ * u_next may alias u_prev2 (but not u_prev).  stats may be NULL.
+ * Errors: EINVAL, ENOTCONV (u_next holds the last iterate), ENONFINITE, EHIP. */
+int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
+               const rsfde_solver_opts* opts, double* u_next, rsfde_stats* stats,
+               void* stream);
+
+/* Solve M x = b for a caller-supplied right-hand side (used by the adjoint
+ * and by tests).  x holds the initial guess on entry and the solution on exit.
+ * Errors: as rsfde_step. */
+int rsfde_solve(rsfde_plan plan, const double* b, double* x, const rsfde_solver_opts* opts,
+                rsfde_stats* stats, void* stream);
+
+/* One reverse step of the discrete adjoint of rsfde_step (no counterpart in
+ * the paper; derived from M u^k = u^{k-1} + dt mask f(u^{k-1}) with M
+ * symmetric, Corollary 2.1 / Lemma 2.3):
+ *   mu       = M^{-1} lam_cur                      (same preconditioned GMRES)
+ *   dk[0]   += < mu, (I (x) A_x/kx) u_cur >         (dL/dkx contribution)
+ *   dk[1]   += < mu, (A_y/ky (x) I) u_cur >         (dL/dky contribution)
+ *   lam_prev = mu + dt * mask * f'(u_prev) * mu
+ * u_prev = u^{k-1}, u_cur = u^k, lam_cur = dL/du^k; dk_dev is a device array of
+ * two doubles accumulated in place.  mu_guess (may be NULL: zero guess) is an
+ * initial guess for mu and receives mu on exit when not NULL.
+ * lam_prev must not alias lam_cur.  Errors: as rsfde_step. */
+int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cur,
+                       const double* lam_cur, int32_t f_kind, const rsfde_solver_opts* opts,
+                       double* lam_prev, double* mu_guess, double* dk_dev, rsfde_stats* stats,
+                       void* stream);
+
+/* Release the plan and all of its memory.  NULL is accepted. */
+int rsfde_destroy(rsfde_plan plan);
+
+/* Static string for an error code. */
+const char* rsfde_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSFDE_H */

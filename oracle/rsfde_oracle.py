@@ -49,6 +49,7 @@ __all__ = [
     "matvec", "tau_hankel", "tau_matrix", "dst1_matrix", "tau_eigenvalues",
     "tau_eigs_dense", "tau_eigs_xy", "precond_dense", "precond_apply", "P_dense",
     "gmres", "march_gmres", "adjoint_lu", "loss_and_grads_lu",
+    "matvec_fast", "precond_apply_fft", "matvec_entry",
     "example1_exact", "example1_source", "example1_march",
     "F_NONE", "F_LOGISTIC", "F_SIN", "F_CUBIC",
 ]
@@ -245,6 +246,28 @@ def matvec(p: Problem, V: np.ndarray, Ax=None, Ay=None) -> np.ndarray:
     return V - V @ Ax.T - Ay @ V + p.d * p.phi * V
 
 
+def matvec_fast(p: Problem, V: np.ndarray) -> np.ndarray:
+    """M v for large grids: the same formula as matvec with the Toeplitz
+    products done by scipy's FFT-based Toeplitz multiply (a library primitive;
+    pinned against matvec in the tests)."""
+    from scipy.linalg import matmul_toeplitz
+    tx = p.cx * toeplitz_first_column(p.alpha1, p.n1)
+    ty = p.cy * toeplitz_first_column(p.alpha2, p.n2)
+    VAx = matmul_toeplitz(tx, V.T).T          # rows: V A_x^T = (A_x V^T)^T
+    AyV = matmul_toeplitz(ty, V)              # columns
+    return V - VAx - AyV + p.d * p.phi * V
+
+
+def matvec_entry(p: Problem, V: np.ndarray, j: int, i: int) -> float:
+    """One entry (row j, column i) of M v, summed directly from (difference_scheme)'s
+    Toeplitz form: O(n1 + n2) work, for sampled checks at any size."""
+    tx = p.cx * toeplitz_first_column(p.alpha1, p.n1)
+    ty = p.cy * toeplitz_first_column(p.alpha2, p.n2)
+    ax = tx[np.abs(np.arange(p.n1) - i)]
+    ay = ty[np.abs(np.arange(p.n2) - j)]
+    return float(V[j, i] - ax @ V[j, :] - ay @ V[:, i] + p.d * p.phi[j, i] * V[j, i])
+
+
 # ---------------------------------------------------------------------------
 # Section 4.1: tau matrices, sine transform, the preconditioner.
 # ---------------------------------------------------------------------------
@@ -320,6 +343,19 @@ def precond_apply(p: Problem, V: np.ndarray, lam=None) -> np.ndarray:
     E2 = E1 + p.d
     Y1 = Sy @ (W / E1) @ Sx
     Y2 = Sy @ (W / E2) @ Sx
+    return (1.0 - p.phi) * Y1 + p.phi * Y2
+
+
+def precond_apply_fft(p: Problem, V: np.ndarray, lam=None) -> np.ndarray:
+    """precond_apply with S_n v taken from scipy's orthonormal DST-I (a library
+    primitive, pinned equal to S_n v in the tests), for large grids."""
+    import scipy.fft as sf
+    lx, ly = tau_eigs_xy(p) if lam is None else lam
+    W = sf.dstn(V, type=1, norm="ortho", workers=-1)
+    E1 = 1.0 - lx[None, :] - ly[:, None]
+    E2 = E1 + p.d
+    Y1 = sf.dstn(W / E1, type=1, norm="ortho", workers=-1)
+    Y2 = sf.dstn(W / E2, type=1, norm="ortho", workers=-1)
     return (1.0 - p.phi) * Y1 + p.phi * Y2
 
 

@@ -1,0 +1,183 @@
+"""ctypes binding of librsfde.so (include/rsfde.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Functions keep the C names and take torch tensors (FP64 / uint8,
+contiguous, on the GPU) or raw device pointers.  Importing this module fails
+loudly if the library has not been built; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsfde.so")
+
+RSFDE_OK = 0
+RSFDE_EINVAL = -1
+RSFDE_ENOMEM = -2
+RSFDE_EHIP = -3
+RSFDE_ENOTCONV = -4
+RSFDE_EBREAKDOWN = -5
+RSFDE_ENONFINITE = -6
+RSFDE_EUNSUPPORTED = -7
+
+RSFDE_FP64, RSFDE_FP32, RSFDE_BF16 = 0, 1, 2
+RSFDE_PRECOND_TAU, RSFDE_PRECOND_NONE = 0, 1
+RSFDE_F_NONE, RSFDE_F_LOGISTIC, RSFDE_F_SIN, RSFDE_F_CUBIC = 0, 1, 2, 3
+
+PRECISIONS = {"fp64": RSFDE_FP64, "fp32": RSFDE_FP32, "bf16": RSFDE_BF16}
+
+
+class rsfde_grid(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("y_lo", C.c_double), ("y_hi", C.c_double)]
+
+
+class rsfde_solver_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
+                ("precision", C.c_int32), ("precond", C.c_int32)]
+
+
+class rsfde_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("relres", C.c_double), ("bnorm", C.c_double)]
+
+
+class RsfdeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(the HIP library is required; there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.rsfde_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,
+                                C.c_double, C.c_double, P, C.c_double, C.c_double, C.c_int32, P]
+    lib.rsfde_set_coeffs.argtypes = [P, C.c_double, C.c_double]
+    lib.rsfde_matvec.argtypes = [P, P, P, P]
+    lib.rsfde_precond_apply.argtypes = [P, P, P, C.c_int32, P]
+    lib.rsfde_step.argtypes = [P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P,
+                               C.POINTER(rsfde_stats), P]
+    lib.rsfde_solve.argtypes = [P, P, P, C.POINTER(rsfde_solver_opts), C.POINTER(rsfde_stats), P]
+    lib.rsfde_adjoint_step.argtypes = [P, P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P, P,
+                                       P, C.POINTER(rsfde_stats), P]
+    lib.rsfde_destroy.argtypes = [P]
+    lib.rsfde_strerror.argtypes = [C.c_int]
+    lib.rsfde_strerror.restype = C.c_char_p
+    for f in ("rsfde_setup", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
+              "rsfde_step", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy"):
+        getattr(lib, f).restype = C.c_int
+    return lib
+
+
+_lib = _load()
+lib = _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.rsfde_strerror(int(code)).decode()
+
+
+def _ptr(x):
+    """Device pointer of a tensor (or an int / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_vec(t, N, name, dtype=None):
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != N:
+        raise ValueError(f"{name}: expected a contiguous {dtype} GPU tensor with {N} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def _raise(rc, where):
+    if rc != RSFDE_OK:
+        raise RsfdeError(rc, where)
+
+
+def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau"):
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
+        if isinstance(precond, str) else int(precond)
+    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc)
+
+
+def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30, stream=None):
+    import torch
+    _check_vec(mask, n1 * n2, "mask", torch.uint8)
+    g = rsfde_grid(int(n1), int(n2), float(box[0]), float(box[1]), float(box[2]), float(box[3]))
+    h = C.c_void_p()
+    rc = _lib.rsfde_setup(C.byref(h), C.byref(g), float(alpha1), float(alpha2), float(kx),
+                          float(ky), _ptr(mask), float(eta), float(dt), int(max_restart),
+                          _stream(stream))
+    _raise(rc, "rsfde_setup")
+    return h
+
+
+def rsfde_set_coeffs(plan, kx, ky):
+    _raise(_lib.rsfde_set_coeffs(plan, float(kx), float(ky)), "rsfde_set_coeffs")
+
+
+def rsfde_matvec(plan, x, y, stream=None):
+    _raise(_lib.rsfde_matvec(plan, _ptr(x), _ptr(y), _stream(stream)), "rsfde_matvec")
+
+
+def rsfde_precond_apply(plan, r, z, precision=RSFDE_FP64, stream=None):
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _raise(_lib.rsfde_precond_apply(plan, _ptr(r), _ptr(z), p, _stream(stream)),
+           "rsfde_precond_apply")
+
+
+def rsfde_step(plan, u_prev, u_prev2, f_kind, opts, u_next, stream=None, check=True):
+    st = rsfde_stats()
+    rc = _lib.rsfde_step(plan, _ptr(u_prev), _ptr(u_prev2), int(f_kind), C.byref(opts),
+                         _ptr(u_next), C.byref(st), _stream(stream))
+    if check:
+        _raise(rc, "rsfde_step")
+    return st
+
+
+def rsfde_solve(plan, b, x, opts, stream=None, check=True):
+    st = rsfde_stats()
+    rc = _lib.rsfde_solve(plan, _ptr(b), _ptr(x), C.byref(opts), C.byref(st), _stream(stream))
+    if check:
+        _raise(rc, "rsfde_solve")
+    return st
+
+
+def rsfde_adjoint_step(plan, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev, mu_guess, dk,
+                       stream=None, check=True):
+    st = rsfde_stats()
+    rc = _lib.rsfde_adjoint_step(plan, _ptr(u_prev), _ptr(u_cur), _ptr(lam_cur), int(f_kind),
+                                 C.byref(opts), _ptr(lam_prev), _ptr(mu_guess), _ptr(dk),
+                                 C.byref(st), _stream(stream))
+    if check:
+        _raise(rc, "rsfde_adjoint_step")
+    return st
+
+
+def rsfde_destroy(plan):
+    _raise(_lib.rsfde_destroy(plan), "rsfde_destroy")

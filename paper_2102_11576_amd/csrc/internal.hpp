@@ -1,0 +1,103 @@
+// Internal declarations shared by the host driver and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fft_engine.hpp"
+
+namespace rsfde {
+
+constexpr int kMaxRestart = 64;       // largest GMRES restart length supported
+constexpr int kRedThreads = 256;      // threads per block of the streaming reductions
+constexpr int kMaxRedBlocks = 2048;   // upper bound on blocks of a streaming reduction
+constexpr int kMinLog2L = 1;          // FFT lengths 2 .. 16384
+constexpr int kMaxLog2L = 14;
+
+// Points per thread of the register-resident FFT of length L.
+constexpr int fft_pts(int L) { return L < 16 ? L : (L >= 8192 ? 8 : 16); }
+// Pass B of the preconditioner keeps half a spectrum in registers besides the
+// FFT data, so it runs radix-8.
+constexpr int pc_cols_pts(int L) { return L < 8 ? L : 8; }
+
+// Values the device writes for the host after each Arnoldi step.  Lives in
+// pinned, device-visible host memory; the host reads it after an event.
+struct HostStatus {
+  double est[kMaxRestart];  // |g_{j+1}|: residual-norm estimate after inner step j
+  double beta;              // ||r|| of the last residual kernel
+  double bnorm;             // ||b||
+  int32_t flags;            // bit 0: non-finite value seen
+  int32_t pad;
+};
+constexpr int kFlagNonFinite = 1;
+
+// Device-side Arnoldi / Givens state.
+struct KrylovState {
+  double H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart + 1
+  double cs[kMaxRestart];
+  double sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double vscale[kMaxRestart + 1];             // V_i is stored unnormalised: v_i = vscale[i] * V_i
+};
+constexpr int kLdH = kMaxRestart + 1;
+
+// Reduction workspace: partial sums and the "last block" ticket counters.
+struct RedWork {
+  double* partial;     // [kMaxRestart + 2][kMaxRedBlocks]
+  unsigned* counters;  // [16]
+};
+
+// ----------------------------- FFT kernels --------------------------------
+// Row pass of the matrix-vector product:
+//   out = coef * (C_x z) + diag * z, diag = (mode==0) ? 1 + dpen (1 - mask) : 0,
+// where C_x is the Toeplitz matrix whose circulant embedding of length L has
+// the symbol `sym` (already divided by L, stored in register-position order).
+hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
+                          const double* sym, const void* tw, int n1, int n2,
+                          double coef, double dpen, int mode, hipStream_t s);
+// Column pass: out = coef * (C_y z) + (mode==0 ? t : 0).
+hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
+                          const double* sym, const void* tw, int n1, int n2,
+                          double coef, int mode, hipStream_t s);
+
+// Sine-transform preconditioner, three passes; T = float or double internally.
+// Pass A: Q[r][slot] = raw x-sine sums of (sig * v) rows.
+template <typename T>
+hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q,
+                              const void* tw, int n1, int n2, hipStream_t s);
+// Pass B: column sine transforms of Q, the two eigenvalue scalings, two inverse
+// column transforms -> P1, P2 (slot layout in x, natural rows in y).
+template <typename T>
+hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
+                          const T* lamy_pos, const void* tw, int n1, int n2,
+                          double kx, double ky, double dpen, double Kfac, hipStream_t s);
+// Pass C: inverse row transforms of P1, P2 and the mask combine -> z (FP64).
+template <typename T>
+hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirror,
+                              const uint8_t* mask, double* z, const void* tw,
+                              int n1, int n2, hipStream_t s);
+
+// ---------------------------- Krylov kernels ------------------------------
+hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
+                      int f_kind, double* b, double* x0, size_t N, RedWork rw,
+                      HostStatus* hs, hipStream_t s);
+hipError_t launch_residual(const double* b, const double* w, double* r, size_t N,
+                           RedWork rw, KrylovState* ks, HostStatus* hs, hipStream_t s);
+hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w, size_t N,
+                           RedWork rw, KrylovState* ks, int j, hipStream_t s);
+hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w,
+                              double* vout, size_t N, RedWork rw, KrylovState* ks, int j,
+                              HostStatus* hs, hipStream_t s);
+hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
+                         KrylovState* ks, hipStream_t s);
+hipError_t launch_scale_copy(const double* v, const double* sig, double* z, size_t N,
+                             hipStream_t s);
+hipError_t launch_adj_lambda(const double* mu, const double* u_prev, const uint8_t* mask,
+                             double dt, int f_kind, double* lam_prev, size_t N, hipStream_t s);
+hipError_t launch_dot_accum(const double* a, const double* b, size_t N, RedWork rw,
+                            int counter_slot, double* acc, hipStream_t s);
+
+int red_blocks(size_t N);
+
+}  // namespace rsfde

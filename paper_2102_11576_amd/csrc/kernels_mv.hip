@@ -1,0 +1,186 @@
+// Matrix-vector product with M = I - A + D (Section 2 of the paper: A is the
+// Kronecker sum I (x) A_x + A_y (x) I of symmetric Toeplitz matrices, D the
+// penalty diagonal dt/eta outside the domain), in two HBM passes:
+//   row pass:    t = (1 + dpen*phi) z - kx * (Ahat_x applied along x)
+//   column pass: w = t - ky * (Ahat_y applied along y)
+// Each Toeplitz product is a circular convolution of length L >= 2n-1 with the
+// real, even symbol of the circulant embedding [t_0..t_{n-1}, 0.., t_{n-1}..t_1]
+// (O(N log N) per product, the fast matrix-vector product the paper relies on).
+// Two real rows (or columns) are packed into one complex FFT: the symbol is
+// real, so real and imaginary parts never mix.
+#include "fft_common.hpp"
+
+namespace rsfde {
+
+template <int L>
+struct MvCfg {
+  using F = Fft<L, fft_pts(L)>;
+  static constexpr int TPF = F::TPF;
+  static constexpr int BR = (256 / TPF) > 0 ? (256 / TPF) : 1;             // FFTs per row block
+  static constexpr int BC = (512 / TPF) > 16 ? 16 : ((512 / TPF) > 0 ? (512 / TPF) : 1);
+  static constexpr int THR_R = BR * TPF;
+  static constexpr int THR_C = BC * TPF;
+};
+
+// --------------------------------------------------------------------------
+// Row pass.  Block = BR FFTs, FFT b handles rows 2*pair and 2*pair+1.
+// --------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(MvCfg<L>::THR_R) void k_mv_rows(
+    const double* __restrict__ z, const uint8_t* __restrict__ mask, double* __restrict__ out,
+    const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
+    double coef, double dpen, int mode) {
+  using C = MvCfg<L>;
+  using F = typename C::F;
+  __shared__ double lds[C::BR * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid / F::TPF, tau = tid % F::TPF;
+  const int pair = blockIdx.x * C::BR + b;
+  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const bool va = ra < n2, vb = rb < n2;
+  const double* za = z + (size_t)ra * n1;
+  const double* zb = z + (size_t)rb * n1;
+  cpx<double> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    const bool in = p < n1;
+    reg[e].re = (va && in) ? za[p] : 0.0;
+    reg[e].im = (vb && in) ? zb[p] : 0.0;
+  });
+  double* my = lds + b * lds_len(L);
+  fft_forward<double, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const double s = sym[F::pos(F::NS - 1, tau, e)] * coef;
+    reg[e].re *= s;
+    reg[e].im *= s;
+  });
+  fft_inverse<double, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (p < n1) {
+      if (va) {
+        const size_t i = (size_t)ra * n1 + p;
+        double v = reg[e].re;
+        if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        out[i] = v;
+      }
+      if (vb) {
+        const size_t i = (size_t)rb * n1 + p;
+        double v = reg[e].im;
+        if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        out[i] = v;
+      }
+    }
+  });
+}
+
+// --------------------------------------------------------------------------
+// Column pass.  Block = BC FFTs over 2*BC adjacent columns; thread layout is
+// (tau, b) with b fastest so that a wavefront reads 2*BC contiguous doubles of
+// several rows at once.
+// --------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(MvCfg<L>::THR_C) void k_mv_cols(
+    const double* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
+    const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
+    double coef, int mode) {
+  using C = MvCfg<L>;
+  using F = typename C::F;
+  __shared__ double lds[C::BC * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid % C::BC, tau = tid / C::BC;
+  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int cp = strip * C::BC + b;
+  const int ca = 2 * cp, cb = 2 * cp + 1;
+  const bool va = ca < n1, vb = cb < n1;
+  cpx<double> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    const bool in = p < n2;
+    reg[e].re = (va && in) ? z[(size_t)p * n1 + ca] : 0.0;
+    reg[e].im = (vb && in) ? z[(size_t)p * n1 + cb] : 0.0;
+  });
+  double* my = lds + b * lds_len(L);
+  fft_forward<double, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const double s = sym[F::pos(F::NS - 1, tau, e)] * coef;
+    reg[e].re *= s;
+    reg[e].im *= s;
+  });
+  fft_inverse<double, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (p < n2) {
+      if (va) {
+        const size_t i = (size_t)p * n1 + ca;
+        out[i] = reg[e].re + (mode == 0 ? t[i] : 0.0);
+      }
+      if (vb) {
+        const size_t i = (size_t)p * n1 + cb;
+        out[i] = reg[e].im + (mode == 0 ? t[i] : 0.0);
+      }
+    }
+  });
+}
+
+template <int L>
+static hipError_t mv_rows_impl(const double* z, const uint8_t* mask, double* out, const double* sym,
+                               const void* tw, int n1, int n2, double coef, double dpen, int mode,
+                               hipStream_t s) {
+  using C = MvCfg<L>;
+  const int pairs = (n2 + 1) / 2;
+  const int blocks = (pairs + C::BR - 1) / C::BR;
+  hipLaunchKernelGGL(k_mv_rows<L>, dim3(blocks), dim3(C::THR_R), 0, s, z, mask, out, sym,
+                     (const cpx<double>*)tw, n1, n2, coef, dpen, mode);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t mv_cols_impl(const double* z, const double* t, double* out, const double* sym,
+                               const void* tw, int n1, int n2, double coef, int mode, hipStream_t s) {
+  using C = MvCfg<L>;
+  const int pairs = (n1 + 1) / 2;
+  const int blocks = (pairs + C::BC - 1) / C::BC;
+  hipLaunchKernelGGL(k_mv_cols<L>, dim3(blocks), dim3(C::THR_C), 0, s, z, t, out, sym,
+                     (const cpx<double>*)tw, n1, n2, coef, mode);
+  return hipGetLastError();
+}
+
+#define RSFDE_L_CASES(X) \
+  X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+
+hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
+                          const double* sym, const void* tw, int n1, int n2, double coef,
+                          double dpen, int mode, hipStream_t s) {
+  switch (L) {
+#define X(LL) \
+  case LL:    \
+    return mv_rows_impl<LL>(z, mask, out, sym, tw, n1, n2, coef, dpen, mode, s);
+    RSFDE_L_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
+                          const double* sym, const void* tw, int n1, int n2, double coef,
+                          int mode, hipStream_t s) {
+  switch (L) {
+#define X(LL) \
+  case LL:    \
+    return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s);
+    RSFDE_L_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rsfde

@@ -1,0 +1,13 @@
+// Preconditioner passes with float internal arithmetic (explicit instantiations).
+#include "pc_kernels.hpp"
+
+namespace rsfde {
+template hipError_t launch_pc_rows_fwd<float>(int, const double*, const double*, float*, const void*,
+                                            int, int, hipStream_t);
+template hipError_t launch_pc_cols<float>(int, const float*, float*, float*, const float*, const float*,
+                                        const void*, int, int, double, double, double, double,
+                                        hipStream_t);
+template hipError_t launch_pc_rows_inv<float>(int, const float*, const float*, const int*,
+                                            const uint8_t*, double*, const void*, int, int,
+                                            hipStream_t);
+}  // namespace rsfde

@@ -1,0 +1,13 @@
+// Preconditioner passes with double internal arithmetic (explicit instantiations).
+#include "pc_kernels.hpp"
+
+namespace rsfde {
+template hipError_t launch_pc_rows_fwd<double>(int, const double*, const double*, double*, const void*,
+                                            int, int, hipStream_t);
+template hipError_t launch_pc_cols<double>(int, const double*, double*, double*, const double*, const double*,
+                                        const void*, int, int, double, double, double, double,
+                                        hipStream_t);
+template hipError_t launch_pc_rows_inv<double>(int, const double*, const double*, const int*,
+                                            const uint8_t*, double*, const void*, int, int,
+                                            hipStream_t);
+}  // namespace rsfde

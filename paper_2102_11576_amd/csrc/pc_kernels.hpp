@@ -1,0 +1,305 @@
+// The sine-transform preconditioner of Section 4.1 of the paper:
+//   P_hat^{-1} = (I - Phi)(I - tau_1(A))^{-1} + Phi((1 + dt/eta) I - tau_1(A))^{-1},
+// with I - tau_1(A) = (S (x) S)(I - I (x) L_x - L_y (x) I)(S (x) S) (Lemma 4.2),
+// applied as three HBM passes over [n2][n1] data:
+//   A (rows):    Q  = raw sine sums of each row of sig*v              (x transform)
+//   B (columns): P1 = S_y( K*rho / E1 ),  P2 = S_y( K*rho / E2 )        (y transform,
+//                rho = raw 2-D sine coefficients, E1 = 1 - kx lx - ky ly, E2 = E1 + dt/eta)
+//   C (rows):    z  = mask * (P1 S_x) + (1 - mask) * (P2 S_x)          (x transform + combine)
+// with K = 4 / ((n1+1)(n2+1)) the product of the orthonormal DST-I factors.
+//
+// A length-n DST-I is one length-L = 2(n+1) complex FFT of the odd extension
+// (x at positions 1..n, -x mirrored, zeros at 0 and n+1): its spectrum is
+// -2i * (raw sine sums).  Two real sequences share one complex FFT (a + i b):
+// the spectrum is 2 sigma_b - 2i sigma_a, both parts odd in frequency.  Pass A
+// stores only the lower half of the digit-reversed spectrum ("slots", n+1 per
+// row: frequencies 0..n, frequency 0 being identically zero); pass B works on
+// slot columns; pass C rebuilds the upper half by odd symmetry (table `mirror`)
+// and runs the inverse sweep, which yields the DST directly in natural order.
+// T = double or float sets the arithmetic of all three passes (the input and
+// output vectors are always FP64).
+#pragma once
+#include "fft_common.hpp"
+
+namespace rsfde {
+
+template <int L>
+struct PcCfg {
+  using F = Fft<L, fft_pts(L)>;
+  static constexpr int TPF = F::TPF;
+  static constexpr int BR = (256 / TPF) > 0 ? (256 / TPF) : 1;
+  static constexpr int THR_R = BR * TPF;
+};
+template <int L>
+struct PcColCfg {
+  using F = Fft<L, pc_cols_pts(L)>;
+  static constexpr int TPF = F::TPF;
+  static constexpr int BC = (512 / TPF) > 16 ? 16 : ((512 / TPF) > 0 ? (512 / TPF) : 1);
+  static constexpr int THR_C = BC * TPF;
+};
+
+// --------------------------------------------------------------------------
+// Pass A: row pairs (ra, rb) -> Q rows (n1+1 slots each).
+// --------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
+    const double* __restrict__ v, const double* __restrict__ sig, T* __restrict__ Q,
+    const cpx<T>* __restrict__ tw, int n1, int n2) {
+  using C = PcCfg<L>;
+  using F = typename C::F;
+  __shared__ T lds[C::BR * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid / F::TPF, tau = tid % F::TPF;
+  const int pair = blockIdx.x * C::BR + b;
+  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const bool va = ra < n2, vb = rb < n2;
+  const double* xa = v + (size_t)ra * n1;
+  const double* xb = v + (size_t)rb * n1;
+  cpx<T> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    // odd extension: x_{p-1} at p in [1, n1], -x_{L-p-1} at p in [n1+2, L-1]
+    int idx = -1;
+    T sgn = (T)1;
+    if (p >= 1 && p <= n1) {
+      idx = p - 1;
+    } else if (p >= n1 + 2) {
+      idx = L - p - 1;
+      sgn = (T)-1;
+    }
+    reg[e].re = (va && idx >= 0) ? sgn * (T)xa[idx] : (T)0;
+    reg[e].im = (vb && idx >= 0) ? sgn * (T)xb[idx] : (T)0;
+  });
+  T* my = lds + b * lds_len(L);
+  fft_forward<T, F>(reg, tau, tw, my);
+  const T s = (T)(0.5 * (sig ? *sig : 1.0));
+  const int ld = n1 + 1;
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    constexpr int R = F::radix(F::NS - 1);
+    if constexpr ((e % R) < R / 2) {
+      const int slot = (tau + (e / R) * F::TPF) * (R / 2) + (e % R);
+      if (va) Q[(size_t)ra * ld + slot] = -reg[e].im * s;  // sigma_a
+      if (vb) Q[(size_t)rb * ld + slot] = reg[e].re * s;   // sigma_b
+    }
+  });
+}
+
+// --------------------------------------------------------------------------
+// Pass B: slot-column pairs (ca, cb) of Q -> P1, P2 columns.
+// --------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
+    const T* __restrict__ Q, T* __restrict__ P1, T* __restrict__ P2,
+    const T* __restrict__ lamx_slot, const T* __restrict__ lamy_pos,
+    const cpx<T>* __restrict__ tw, int n1, int n2, T kx, T ky, T dpen, T halfK) {
+  using C = PcColCfg<L>;
+  using F = typename C::F;
+  __shared__ T lds[C::BC * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid % C::BC, tau = tid / C::BC;
+  const int strip = xcd_remap(blockIdx.x, gridDim.x);
+  const int cp = strip * C::BC + b;
+  const int ca = 2 * cp, cb = 2 * cp + 1;
+  const int ld = n1 + 1;
+  const bool valid = cb < ld;  // n1 + 1 is even: both or neither
+  cpx<T> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    int row = -1;
+    T sgn = (T)1;
+    if (p >= 1 && p <= n2) {
+      row = p - 1;
+    } else if (p >= n2 + 2) {
+      row = L - p - 1;
+      sgn = (T)-1;
+    }
+    const bool ok = valid && row >= 0;
+    reg[e].re = ok ? sgn * Q[(size_t)row * ld + ca] : (T)0;
+    reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
+  });
+  T* my = lds + b * lds_len(L);
+  fft_forward<T, F>(reg, tau, tw, my);
+  // spectrum = 2 rho_b - 2i rho_a; keep rho_b for the second column
+  const T lxa = valid ? kx * lamx_slot[ca] : (T)0;
+  const T lxb = valid ? kx * lamx_slot[cb] : (T)0;
+  T rho_b[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const T ly = ky * lamy_pos[F::pos(F::NS - 1, tau, e)];
+    const T rho_a = (T)-0.5 * reg[e].im;
+    rho_b[e] = (T)0.5 * reg[e].re;
+    const T e1 = (T)1 - lxa - ly;
+    const T e2 = e1 + dpen;
+    const T r = halfK * rho_a / (e1 * e2);
+    // (K rho / 2) (1/E2 - i/E1)
+    reg[e].re = r * e1;
+    reg[e].im = -r * e2;
+  });
+  fft_inverse<T, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (valid && p >= 1 && p <= n2) {
+      const size_t i = (size_t)(p - 1) * ld + ca;
+      P1[i] = reg[e].re;
+      P2[i] = reg[e].im;
+    }
+  });
+  // Hide the table pointer from the optimiser so that the second sweep reloads
+  // its twiddles instead of keeping the first sweep's in registers.
+  const cpx<T>* tw2 = tw;
+  const T* lamy2 = lamy_pos;
+  asm volatile("" : "+s"(tw2), "+s"(lamy2));
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const T ly = ky * lamy2[F::pos(F::NS - 1, tau, e)];
+    const T e1 = (T)1 - lxb - ly;
+    const T e2 = e1 + dpen;
+    const T r = halfK * rho_b[e] / (e1 * e2);
+    reg[e].re = r * e1;
+    reg[e].im = -r * e2;
+  });
+  fft_inverse<T, F>(reg, tau, tw2, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (valid && p >= 1 && p <= n2) {
+      const size_t i = (size_t)(p - 1) * ld + cb;
+      P1[i] = reg[e].re;
+      P2[i] = reg[e].im;
+    }
+  });
+}
+
+// --------------------------------------------------------------------------
+// Pass C: one row r per FFT; spectrum P2/2 - i P1/2 on the lower half, odd
+// mirror on the upper half; the inverse sweep gives (P1 S_x) + i (P2 S_x).
+// --------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
+    const T* __restrict__ P1, const T* __restrict__ P2, const int* __restrict__ mirror,
+    const uint8_t* __restrict__ mask, double* __restrict__ z, const cpx<T>* __restrict__ tw,
+    int n1, int n2) {
+  using C = PcCfg<L>;
+  using F = typename C::F;
+  __shared__ T lds[C::BR * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid / F::TPF, tau = tid % F::TPF;
+  const int r = blockIdx.x * C::BR + b;
+  const bool vr = r < n2;
+  const int ld = n1 + 1;
+  const T* p1 = P1 + (size_t)r * ld;
+  const T* p2 = P2 + (size_t)r * ld;
+  cpx<T> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    constexpr int R = F::radix(F::NS - 1);
+    if constexpr ((e % R) < R / 2) {
+      const int slot = (tau + (e / R) * F::TPF) * (R / 2) + (e % R);
+      reg[e].re = vr ? (T)0.5 * p2[slot] : (T)0;
+      reg[e].im = vr ? (T)-0.5 * p1[slot] : (T)0;
+    } else {
+      const int ms = mirror[F::pos(F::NS - 1, tau, e)];
+      const bool ok = vr && ms >= 0;
+      reg[e].re = ok ? (T)-0.5 * p2[ms] : (T)0;
+      reg[e].im = ok ? (T)0.5 * p1[ms] : (T)0;
+    }
+  });
+  T* my = lds + b * lds_len(L);
+  fft_inverse<T, F>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (vr && p >= 1 && p <= n1) {
+      const size_t i = (size_t)r * n1 + (p - 1);
+      z[i] = mask[i] ? (double)reg[e].re : (double)reg[e].im;
+    }
+  });
+}
+
+// ------------------------------- launchers --------------------------------
+template <typename T, int L>
+static hipError_t pc_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* tw,
+                                   int n1, int n2, hipStream_t s) {
+  using C = PcCfg<L>;
+  const int pairs = (n2 + 1) / 2;
+  const int blocks = (pairs + C::BR - 1) / C::BR;
+  hipLaunchKernelGGL((k_pc_rows_fwd<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, v, sig, Q,
+                     (const cpx<T>*)tw, n1, n2);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t pc_cols_impl(const T* Q, T* P1, T* P2, const T* lamx, const T* lamy,
+                               const void* tw, int n1, int n2, double kx, double ky, double dpen,
+                               double Kfac, hipStream_t s) {
+  using C = PcColCfg<L>;
+  const int pairs = (n1 + 1) / 2;
+  const int blocks = (pairs + C::BC - 1) / C::BC;
+  hipLaunchKernelGGL((k_pc_cols<T, L>), dim3(blocks), dim3(C::THR_C), 0, s, Q, P1, P2, lamx, lamy,
+                     (const cpx<T>*)tw, n1, n2, (T)kx, (T)ky, (T)dpen, (T)(0.5 * Kfac));
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t pc_rows_inv_impl(const T* P1, const T* P2, const int* mirror,
+                                   const uint8_t* mask, double* z, const void* tw, int n1, int n2,
+                                   hipStream_t s) {
+  using C = PcCfg<L>;
+  const int blocks = (n2 + C::BR - 1) / C::BR;
+  hipLaunchKernelGGL((k_pc_rows_inv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2, mirror,
+                     mask, z, (const cpx<T>*)tw, n1, n2);
+  return hipGetLastError();
+}
+
+#define RSFDE_LD_CASES(X) \
+  X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+
+template <typename T>
+hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, const void* tw,
+                              int n1, int n2, hipStream_t s) {
+  switch (Lx) {
+#define X(LL) \
+  case LL:    \
+    return pc_rows_fwd_impl<T, LL>(v, sig, Q, tw, n1, n2, s);
+    RSFDE_LD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
+                          const T* lamy_pos, const void* tw, int n1, int n2, double kx, double ky,
+                          double dpen, double Kfac, hipStream_t s) {
+  switch (Ly) {
+#define X(LL) \
+  case LL:    \
+    return pc_cols_impl<T, LL>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, dpen, Kfac, s);
+    RSFDE_LD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirror,
+                              const uint8_t* mask, double* z, const void* tw, int n1, int n2,
+                              hipStream_t s) {
+  switch (Lx) {
+#define X(LL) \
+  case LL:    \
+    return pc_rows_inv_impl<T, LL>(P1, P2, mirror, mask, z, tw, n1, n2, s);
+    RSFDE_LD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rsfde

@@ -1,0 +1,602 @@
+// Host side of librsfde: plan construction (coefficients, symbols, eigenvalue
+// tables), the restarted flexible GMRES driver and the C ABI of rsfde.h.
+//
+// Set-up follows Section 2 (grid, Grunwald-Letnikov weights (g_form), the
+// Toeplitz first column of (G), c_x = dt kx c_alpha / h_x^alpha) and Section 4.1
+// (tau-matrix eigenvalues from the first column).  Everything is computed once
+// in FP64 on the host, with exact argument reduction of the cosines, and
+// uploaded as O(n) tables; kx and ky enter only as scalars at apply time.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/rsfde.h"
+#include "internal.hpp"
+
+namespace rsfde {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+int next_pow2(long v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define CK(expr)                                   \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return RSFDE_EHIP;       \
+  } while (0)
+
+// cos(2 pi k / L) for k < L, with exact integer argument reduction by the caller.
+std::vector<double> cos_table(int L) {
+  std::vector<double> c(L);
+  for (int k = 0; k < L; ++k) {
+    // reduce to the first octant-free form: angle = 2 pi k / L in [0, 2 pi)
+    c[k] = std::cos(2.0 * kPi * (double)k / (double)L);
+  }
+  // make the symmetric values exactly symmetric
+  for (int k = 1; k < L; ++k) c[L - k] = c[k] = (k <= L - k) ? c[k] : c[L - k];
+  return c;
+}
+
+}  // namespace
+
+struct Plan {
+  int dev = 0;
+  hipStream_t s0 = nullptr;
+  int n1 = 0, n2 = 0;
+  size_t N = 0, ldv = 0;
+  double alpha1 = 0, alpha2 = 0, kx = 0, ky = 0, eta = 0, dt = 0, dpen = 0;
+  int Lcx = 0, Lcy = 0, Ldx = 0, Ldy = 0;
+  int max_restart = 0;
+
+  uint8_t* mask = nullptr;
+  double* V = nullptr;
+  double* Z = nullptr;
+  double* b = nullptr;
+  double* w = nullptr;
+  double* t = nullptr;
+  double* mu = nullptr;
+  void* Q = nullptr;
+  void* P1 = nullptr;
+  void* P2 = nullptr;
+  double* symx = nullptr;
+  double* symy = nullptr;
+  double* lamx64 = nullptr;
+  double* lamy64 = nullptr;
+  float* lamx32 = nullptr;
+  float* lamy32 = nullptr;
+  int* mirror = nullptr;
+  std::map<int, void*> tw64, tw32;
+  KrylovState* ks = nullptr;
+  RedWork rw{nullptr, nullptr};
+  HostStatus* hs = nullptr;      // pinned host memory
+  HostStatus* hs_dev = nullptr;  // its device-visible address
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<void*> allocs;
+
+  ~Plan() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hs) (void)hipHostFree(hs);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  template <typename T>
+  hipError_t dalloc(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    *p = (T*)q;
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
+
+// First column of the unit-coefficient Toeplitz matrix c * G_n^(alpha) (G).
+std::vector<double> toeplitz_col(double alpha, int n, double c) {
+  std::vector<double> g(n + 2);
+  g[0] = 1.0;
+  for (int l = 1; l < n + 2; ++l) g[l] = (1.0 - (alpha + 1.0) / l) * g[l - 1];
+  std::vector<double> t(n);
+  t[0] = 2.0 * g[1];
+  if (n > 1) t[1] = g[0] + g[2];
+  for (int k = 2; k < n; ++k) t[k] = g[k + 1];
+  for (auto& v : t) v *= c;
+  return t;
+}
+
+// Symbol of the circulant embedding of length L (L >= 2n - 1) of the symmetric
+// Toeplitz matrix with first column t, divided by L, in the register-position
+// order of the FFT of length L.
+std::vector<double> conv_symbol_pos(const std::vector<double>& t, int L) {
+  const int n = (int)t.size();
+  std::vector<double> ct = cos_table(L), chat(L);
+  for (int f = 0; f < L; ++f) {
+    double s = t[0];
+    for (int j = 1; j < n; ++j) s += 2.0 * t[j] * ct[(int)(((long long)j * f) % L)];
+    chat[f] = s;
+  }
+  const int P = fft_pts(L);
+  std::vector<double> out(L);
+  for (int p = 0; p < L; ++p) out[p] = chat[fft_freq(L, P, p)] / (double)L;
+  return out;
+}
+
+// Eigenvalues of tau(T_n) for k = 1..n (index k-1): t_0 + 2 sum_j t_j cos(j k pi/(n+1)).
+std::vector<double> tau_eigs(const std::vector<double>& t) {
+  const int n = (int)t.size();
+  const int L = 2 * (n + 1);
+  std::vector<double> ct = cos_table(L), lam(n);
+  for (int k = 1; k <= n; ++k) {
+    double s = t[0];
+    for (int j = 1; j < n; ++j) s += 2.0 * t[j] * ct[(int)(((long long)j * k) % L)];
+    lam[k - 1] = s;
+  }
+  return lam;
+}
+
+template <typename T>
+std::vector<T> twiddles(int L) {
+  std::vector<T> tw(2 * (size_t)L);
+  for (int j = 0; j < L; ++j) {
+    // exp(-2 pi i j / L) with exact symmetry in j
+    const int jj = j <= L / 2 ? j : L - j;
+    const double a = 2.0 * kPi * (double)jj / (double)L;
+    double c = std::cos(a), s = std::sin(a);
+    if (4 * jj == L) c = 0.0;
+    if (2 * jj == L) s = 0.0;
+    tw[2 * (size_t)j] = (T)c;
+    tw[2 * (size_t)j + 1] = (T)(j <= L / 2 ? -s : s);
+  }
+  return tw;
+}
+
+template <typename T>
+hipError_t upload(Plan* P, T** dst, const std::vector<T>& src, hipStream_t s) {
+  hipError_t e = P->dalloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
+  if (L <= 0 || P->tw64.count(L)) return hipSuccess;
+  double* d = nullptr;
+  float* f = nullptr;
+  hipError_t e = upload(P, &d, twiddles<double>(L), s);
+  if (e != hipSuccess) return e;
+  e = upload(P, &f, twiddles<float>(L), s);
+  if (e != hipSuccess) return e;
+  P->tw64[L] = d;
+  P->tw32[L] = f;
+  return hipSuccess;
+}
+
+int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s) {
+  CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
+                    P->dpen, 0, s));
+  CK(launch_mv_cols(P->Lcy, x, P->t, y, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+  return RSFDE_OK;
+}
+
+int precond_impl(Plan* P, const double* r, const double* sig, double* z, int precision,
+                 hipStream_t s) {
+  if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
+  const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
+  if (precision == RSFDE_FP64) {
+    double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
+    CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
+    CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
+                              P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw64[P->Ldx], P->n1,
+                                  P->n2, s));
+    return RSFDE_OK;
+  }
+  if (precision == RSFDE_FP32) {
+    float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
+    CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
+    CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
+                             P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw32[P->Ldx], P->n1,
+                                 P->n2, s));
+    return RSFDE_OK;
+  }
+  return RSFDE_EUNSUPPORTED;
+}
+
+int validate_opts(Plan* P, const rsfde_solver_opts* o) {
+  if (!o) return RSFDE_EINVAL;
+  if (o->restart < 1 || o->restart > P->max_restart) return RSFDE_EINVAL;
+  if (o->max_iters < 1) return RSFDE_EINVAL;
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RSFDE_EINVAL;
+  if (o->precond != RSFDE_PRECOND_TAU && o->precond != RSFDE_PRECOND_NONE) return RSFDE_EINVAL;
+  if (o->precision < RSFDE_FP64 || o->precision > RSFDE_BF16) return RSFDE_EINVAL;
+  if (o->precond == RSFDE_PRECOND_TAU) {
+    if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
+    if (o->precision == RSFDE_BF16) return RSFDE_EUNSUPPORTED;
+  }
+  return RSFDE_OK;
+}
+
+double vread(const volatile double* p) { return *p; }
+int vread(const volatile int32_t* p) { return *p; }
+
+int finish(rsfde_stats* st, int code, int iters, int restarts, double beta, double bnorm) {
+  if (st) {
+    st->iters = iters;
+    st->restarts = restarts;
+    st->status = code;
+    st->reserved = 0;
+    st->relres = bnorm > 0.0 ? beta / bnorm : 0.0;
+    st->bnorm = bnorm;
+  }
+  return code;
+}
+
+// Restarted right-preconditioned flexible GMRES on M x = P->b (bnorm already
+// in hs->bnorm).  x holds the initial guess and receives the solution.
+int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s) {
+  const size_t N = P->N, ld = P->ldv;
+  volatile HostStatus* hs = P->hs;
+  CK(hipStreamSynchronize(s));
+  if (vread(&hs->flags) & kFlagNonFinite) return finish(st, RSFDE_ENONFINITE, 0, 0, 0, 0);
+  const double bnorm = vread(&hs->bnorm);
+  if (bnorm == 0.0) {
+    CK(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    CK(hipStreamSynchronize(s));
+    return finish(st, RSFDE_OK, 0, 0, 0.0, 0.0);
+  }
+  const double thresh = o->tol * bnorm;
+  int total = 0, cycles = 0;
+  double beta = 0.0;
+  for (;;) {
+    int rc = matvec_impl(P, x, P->w, s);
+    if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+    CK(launch_residual(P->b, P->w, P->V, N, P->rw, P->ks, P->hs_dev, s));
+    CK(hipStreamSynchronize(s));
+    if (vread(&hs->flags) & kFlagNonFinite) return finish(st, RSFDE_ENONFINITE, total, cycles, beta, bnorm);
+    beta = vread(&hs->beta);
+    if (beta <= thresh) return finish(st, RSFDE_OK, total, cycles, beta, bnorm);
+    if (total >= o->max_iters) return finish(st, RSFDE_ENOTCONV, total, cycles, beta, bnorm);
+    ++cycles;
+    const int jmax = std::min(o->restart, o->max_iters - total);
+    int jc = -1;
+    for (int j = 0; j < jmax; ++j) {
+      double* vj = P->V + (size_t)j * ld;
+      double* zj = P->Z + (size_t)j * ld;
+      const double* sig = &P->ks->vscale[j];
+      if (o->precond == RSFDE_PRECOND_TAU) {
+        rc = precond_impl(P, vj, sig, zj, o->precision, s);
+        if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+      } else {
+        CK(launch_scale_copy(vj, sig, zj, N, s));
+      }
+      rc = matvec_impl(P, zj, P->w, s);
+      if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+      CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, s));
+      CK(launch_axpy_givens(P->V, ld, j + 1, P->w, P->V + (size_t)(j + 1) * ld, N, P->rw, P->ks,
+                            j, P->hs_dev, s));
+      CK(hipEventRecord(P->ev[j & 1], s));
+      // Look one iteration behind: the device runs step j while the host
+      // checks step j-1.  A converged j-1 leaves step j's work unused
+      // (it writes only column j and vectors j, j+1).
+      if (j > 0) {
+        CK(hipEventSynchronize(P->ev[(j - 1) & 1]));
+        if (vread(&hs->flags) & kFlagNonFinite)
+          return finish(st, RSFDE_ENONFINITE, total + j, cycles, beta, bnorm);
+        if (vread(&hs->est[j - 1]) <= thresh) {
+          jc = j;
+          break;
+        }
+      }
+    }
+    if (jc < 0) {
+      CK(hipEventSynchronize(P->ev[(jmax - 1) & 1]));
+      if (vread(&hs->flags) & kFlagNonFinite)
+        return finish(st, RSFDE_ENONFINITE, total + jmax, cycles, beta, bnorm);
+      jc = jmax;
+    }
+    CK(launch_update(P->Z, ld, jc, x, N, P->ks, s));
+    total += jc;
+  }
+}
+
+}  // namespace
+}  // namespace rsfde
+
+using rsfde::Plan;
+
+struct rsfde_plan_s {
+  Plan p;
+};
+
+extern "C" {
+
+const char* rsfde_strerror(int code) {
+  switch (code) {
+    case RSFDE_OK: return "ok";
+    case RSFDE_EINVAL: return "invalid argument";
+    case RSFDE_ENOMEM: return "out of memory";
+    case RSFDE_EHIP: return "HIP runtime error";
+    case RSFDE_ENOTCONV: return "iteration cap reached before convergence";
+    case RSFDE_EBREAKDOWN: return "Krylov breakdown";
+    case RSFDE_ENONFINITE: return "non-finite value";
+    case RSFDE_EUNSUPPORTED: return "unsupported shape or option";
+    default: return "unknown error";
+  }
+}
+
+int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double alpha2,
+                double kx, double ky, const uint8_t* mask_dev, double eta, double dt,
+                int32_t max_restart, void* stream) {
+  using namespace rsfde;
+  if (!out) return RSFDE_EINVAL;
+  *out = nullptr;
+  if (!grid || !mask_dev) return RSFDE_EINVAL;
+  const int n1 = grid->n1, n2 = grid->n2;
+  if (n1 < 1 || n2 < 1) return RSFDE_EINVAL;
+  if (!(grid->x_hi > grid->x_lo) || !(grid->y_hi > grid->y_lo)) return RSFDE_EINVAL;
+  if (!std::isfinite(grid->x_lo) || !std::isfinite(grid->x_hi) || !std::isfinite(grid->y_lo) ||
+      !std::isfinite(grid->y_hi))
+    return RSFDE_EINVAL;
+  if (!(alpha1 > 1.0 && alpha1 < 2.0) || !(alpha2 > 1.0 && alpha2 < 2.0)) return RSFDE_EINVAL;
+  if (!(kx >= 0.0) || !(ky >= 0.0) || !std::isfinite(kx) || !std::isfinite(ky)) return RSFDE_EINVAL;
+  if (!(eta > 0.0) || !(dt > 0.0) || !std::isfinite(eta) || !std::isfinite(dt)) return RSFDE_EINVAL;
+  if (max_restart <= 0) max_restart = 30;
+  if (max_restart > kMaxRestart) return RSFDE_EINVAL;
+  if (n1 > 8191 || n2 > 8191) return RSFDE_EUNSUPPORTED;
+
+  rsfde_plan_s* h = new (std::nothrow) rsfde_plan_s();
+  if (!h) return RSFDE_ENOMEM;
+  Plan* P = &h->p;
+  int rc = RSFDE_OK;
+  auto fail = [&](int code) {
+    delete h;
+    return code;
+  };
+  if (hipGetDevice(&P->dev) != hipSuccess) return fail(RSFDE_EHIP);
+  hipStream_t s = (hipStream_t)stream;
+  P->s0 = s;
+  P->n1 = n1;
+  P->n2 = n2;
+  P->N = (size_t)n1 * (size_t)n2;
+  P->ldv = (P->N + 63) / 64 * 64;
+  P->alpha1 = alpha1;
+  P->alpha2 = alpha2;
+  P->kx = kx;
+  P->ky = ky;
+  P->eta = eta;
+  P->dt = dt;
+  P->dpen = dt / eta;
+  P->max_restart = max_restart;
+
+  // Section 2: mesh widths and unit-k coefficients c = dt c_alpha / h^alpha.
+  const double hx = (grid->x_hi - grid->x_lo) / (n1 + 1);
+  const double hy = (grid->y_hi - grid->y_lo) / (n2 + 1);
+  const double ca1 = -1.0 / (2.0 * std::cos(alpha1 * kPi / 2.0));
+  const double ca2 = -1.0 / (2.0 * std::cos(alpha2 * kPi / 2.0));
+  const double cx1 = dt * ca1 / std::pow(hx, alpha1);
+  const double cy1 = dt * ca2 / std::pow(hy, alpha2);
+  const std::vector<double> tx = toeplitz_col(alpha1, n1, cx1);
+  const std::vector<double> ty = toeplitz_col(alpha2, n2, cy1);
+
+  P->Lcx = std::max(2, next_pow2(2L * n1));
+  P->Lcy = std::max(2, next_pow2(2L * n2));
+  P->Ldx = is_pow2(n1 + 1) ? 2 * (n1 + 1) : 0;
+  P->Ldy = is_pow2(n2 + 1) ? 2 * (n2 + 1) : 0;
+
+  const size_t N = P->N, ld = P->ldv;
+  const size_t slots = (size_t)(n1 + 1) * (size_t)n2;
+#define AL(ptr, cnt)                                              \
+  do {                                                            \
+    if (P->dalloc(&(ptr), (cnt)) != hipSuccess) return fail(RSFDE_ENOMEM); \
+  } while (0)
+  AL(P->mask, N);
+  AL(P->V, (size_t)(max_restart + 1) * ld);
+  AL(P->Z, (size_t)max_restart * ld);
+  AL(P->b, ld);
+  AL(P->w, ld);
+  AL(P->t, ld);
+  AL(P->mu, ld);
+  double* q = nullptr;
+  AL(q, slots);
+  P->Q = q;
+  AL(q, slots);
+  P->P1 = q;
+  AL(q, slots);
+  P->P2 = q;
+  AL(P->ks, 1);
+  AL(P->rw.partial, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
+  AL(P->rw.counters, 16);
+#undef AL
+  if (hipHostMalloc((void**)&P->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return fail(RSFDE_ENOMEM);
+  std::memset((void*)P->hs, 0, sizeof(HostStatus));
+  if (hipHostGetDevicePointer((void**)&P->hs_dev, P->hs, 0) != hipSuccess) return fail(RSFDE_EHIP);
+  for (auto& e : P->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RSFDE_EHIP);
+
+  if (hipMemcpyAsync(P->mask, mask_dev, N, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(RSFDE_EHIP);
+  if (hipMemsetAsync(P->rw.counters, 0, 16 * sizeof(unsigned), s) != hipSuccess) return fail(RSFDE_EHIP);
+  if (hipMemsetAsync(P->ks, 0, sizeof(KrylovState), s) != hipSuccess) return fail(RSFDE_EHIP);
+
+  // Matrix-vector symbols (unit kx, ky).
+  if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return fail(RSFDE_ENOMEM);
+  if (upload(P, &P->symy, conv_symbol_pos(ty, P->Lcy), s) != hipSuccess) return fail(RSFDE_ENOMEM);
+  for (int L : {P->Lcx, P->Lcy, P->Ldx, P->Ldy})
+    if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
+
+  // Preconditioner tables (Section 4.1), in the layouts of the three passes.
+  if (P->Ldx && P->Ldy) {
+    const std::vector<double> lx = tau_eigs(tx), ly = tau_eigs(ty);
+    const int Lx = P->Ldx, Px = fft_pts(Lx);
+    const int Ly = P->Ldy, Py = pc_cols_pts(Ly);
+    std::vector<double> lamx(n1 + 1), lamy(Ly);
+    std::vector<int> slot_of_f(Lx / 2, -1), mirror(Lx, -1);
+    for (int c = 0; c < n1 + 1; ++c) {
+      const int f = fft_freq(Lx, Px, fft_slot_pos(Lx, Px, c));
+      lamx[c] = (f >= 1 && f <= n1) ? lx[f - 1] : 0.0;
+      slot_of_f[f] = c;
+    }
+    for (int p = 0; p < Lx; ++p) {
+      const int f = fft_freq(Lx, Px, p);
+      if (f >= Lx / 2) {
+        const int g = Lx - f;
+        mirror[p] = (g == Lx / 2) ? -1 : slot_of_f[g];
+      }
+    }
+    for (int p = 0; p < Ly; ++p) {
+      const int f = fft_freq(Ly, Py, p);
+      const int g = std::min(f, Ly - f);
+      lamy[p] = (g >= 1 && g <= n2) ? ly[g - 1] : 0.0;
+    }
+    std::vector<float> lamx_f(lamx.begin(), lamx.end()), lamy_f(lamy.begin(), lamy.end());
+    if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
+        upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess ||
+        upload(P, &P->mirror, mirror, s) != hipSuccess)
+      return fail(RSFDE_ENOMEM);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(RSFDE_EHIP);
+  (void)rc;
+  *out = h;
+  return RSFDE_OK;
+}
+
+int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky) {
+  if (!plan) return RSFDE_EINVAL;
+  if (!(kx >= 0.0) || !(ky >= 0.0) || !std::isfinite(kx) || !std::isfinite(ky)) return RSFDE_EINVAL;
+  plan->p.kx = kx;
+  plan->p.ky = ky;
+  return RSFDE_OK;
+}
+
+int rsfde_matvec(rsfde_plan plan, const double* x, double* y, void* stream) {
+  if (!plan || !x || !y || x == y) return RSFDE_EINVAL;
+  Plan* P = &plan->p;
+  rsfde::DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  return rsfde::matvec_impl(P, x, y, rsfde::pick(P, stream));
+}
+
+int rsfde_precond_apply(rsfde_plan plan, const double* r, double* z, int32_t precision,
+                        void* stream) {
+  if (!plan || !r || !z || r == z) return RSFDE_EINVAL;
+  if (precision < RSFDE_FP64 || precision > RSFDE_BF16) return RSFDE_EINVAL;
+  Plan* P = &plan->p;
+  rsfde::DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  return rsfde::precond_impl(P, r, nullptr, z, precision, rsfde::pick(P, stream));
+}
+
+int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
+               const rsfde_solver_opts* opts, double* u_next, rsfde_stats* stats, void* stream) {
+  using namespace rsfde;
+  if (!plan || !u_prev || !u_next || u_next == u_prev) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_CUBIC) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  Plan* P = &plan->p;
+  int rc = validate_opts(P, opts);
+  if (rc) return finish(stats, rc, 0, 0, 0, 0);
+  DeviceGuard g(P->dev);
+  if (!g.ok) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  hipStream_t s = pick(P, stream);
+  P->hs->flags = 0;
+  if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, P->b, u_next, P->N, P->rw, P->hs_dev, s) !=
+      hipSuccess)
+    return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  return solve_core(P, u_next, opts, stats, s);
+}
+
+int rsfde_solve(rsfde_plan plan, const double* b, double* x, const rsfde_solver_opts* opts,
+                rsfde_stats* stats, void* stream) {
+  using namespace rsfde;
+  if (!plan || !b || !x || b == x) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  Plan* P = &plan->p;
+  int rc = validate_opts(P, opts);
+  if (rc) return finish(stats, rc, 0, 0, 0, 0);
+  DeviceGuard g(P->dev);
+  if (!g.ok) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  hipStream_t s = pick(P, stream);
+  P->hs->flags = 0;
+  // copy b into the plan and take its norm (f = 0, dt = 0: b = u, x0 -> scratch)
+  if (launch_rhs(b, nullptr, P->mask, 0.0, RSFDE_F_NONE, P->b, P->t, P->N, P->rw, P->hs_dev, s) !=
+      hipSuccess)
+    return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  return solve_core(P, x, opts, stats, s);
+}
+
+int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cur,
+                       const double* lam_cur, int32_t f_kind, const rsfde_solver_opts* opts,
+                       double* lam_prev, double* mu_guess, double* dk_dev, rsfde_stats* stats,
+                       void* stream) {
+  using namespace rsfde;
+  if (!plan || !u_prev || !u_cur || !lam_cur || !lam_prev || !dk_dev || lam_prev == lam_cur)
+    return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_CUBIC) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  Plan* P = &plan->p;
+  int rc = validate_opts(P, opts);
+  if (rc) return finish(stats, rc, 0, 0, 0, 0);
+  DeviceGuard g(P->dev);
+  if (!g.ok) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  hipStream_t s = pick(P, stream);
+  double* mu = mu_guess ? mu_guess : P->mu;
+  if (!mu_guess && hipMemsetAsync(mu, 0, P->N * sizeof(double), s) != hipSuccess)
+    return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  P->hs->flags = 0;
+  if (launch_rhs(lam_cur, nullptr, P->mask, 0.0, RSFDE_F_NONE, P->b, P->t, P->N, P->rw, P->hs_dev,
+                 s) != hipSuccess)
+    return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  rc = solve_core(P, mu, opts, stats, s);
+  if (rc != RSFDE_OK) return rc;
+  // directional derivatives of M with respect to kx and ky, dotted with mu
+  if (launch_mv_rows(P->Lcx, u_cur, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, 1.0, 0.0,
+                     1, s) != hipSuccess ||
+      launch_dot_accum(mu, P->t, P->N, P->rw, 4, dk_dev, s) != hipSuccess ||
+      launch_mv_cols(P->Lcy, u_cur, nullptr, P->t, P->symy, P->tw64[P->Lcy], P->n1, P->n2, 1.0, 1,
+                     s) != hipSuccess ||
+      launch_dot_accum(mu, P->t, P->N, P->rw, 5, dk_dev + 1, s) != hipSuccess ||
+      launch_adj_lambda(mu, u_prev, P->mask, P->dt, f_kind, lam_prev, P->N, s) != hipSuccess)
+    return finish(stats, RSFDE_EHIP, stats ? stats->iters : 0, 0, 0, 0);
+  if (hipStreamSynchronize(s) != hipSuccess) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  return RSFDE_OK;
+}
+
+int rsfde_destroy(rsfde_plan plan) {
+  if (!plan) return RSFDE_OK;
+  int dev = plan->p.dev;
+  {
+    rsfde::DeviceGuard g(dev);
+    (void)hipDeviceSynchronize();
+  }
+  delete plan;
+  return RSFDE_OK;
+}
+
+}  // extern "C"

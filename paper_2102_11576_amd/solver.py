@@ -1,0 +1,137 @@
+"""Thin Python wrapper over the C ABI: a plan object and the time march.
+
+Only device memory, streams and the loop over time steps live here; every
+arithmetic step runs in librsfde's HIP kernels.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class StepStats:
+    iters: int
+    restarts: int
+    relres: float
+    status: int
+
+
+class RsfdePlan:
+    """Owns one rsfde_plan (device workspaces, tables) for a grid and parameters."""
+
+    def __init__(self, n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30,
+                 device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        if not isinstance(mask, torch.Tensor):
+            mask = torch.as_tensor(mask)
+        self.mask = mask.to(device=dev, dtype=torch.uint8).contiguous().reshape(-1)
+        self.n1, self.n2 = int(n1), int(n2)
+        self.box = tuple(float(v) for v in box)
+        self.alpha1, self.alpha2 = float(alpha1), float(alpha2)
+        self.kx, self.ky = float(kx), float(ky)
+        self.eta, self.dt = float(eta), float(dt)
+        self.device = dev
+        with torch.cuda.device(dev):
+            self.handle = L.rsfde_setup(self.n1, self.n2, self.box, alpha1, alpha2, kx, ky,
+                                        self.mask, eta, dt, max_restart)
+
+    @classmethod
+    def from_workload(cls, w, kx=None, ky=None, max_restart=None, device=None):
+        mask = torch.as_tensor(w.mask)
+        return cls(w.n1, w.n2, w.box, w.alpha1, w.alpha2, w.kx if kx is None else kx,
+                   w.ky if ky is None else ky, mask, w.eta, w.T / w.m,
+                   w.restart if max_restart is None else max_restart, device)
+
+    @property
+    def N(self):
+        return self.n1 * self.n2
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            L.rsfde_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_coeffs(self, kx, ky):
+        L.rsfde_set_coeffs(self.handle, kx, ky)
+        self.kx, self.ky = float(kx), float(ky)
+
+    def empty(self):
+        return torch.empty(self.N, dtype=torch.float64, device=self.device)
+
+    def matvec(self, x, y=None):
+        y = self.empty() if y is None else y
+        L._check_vec(x, self.N, "x")
+        L._check_vec(y, self.N, "y")
+        L.rsfde_matvec(self.handle, x, y)
+        return y
+
+    def precond(self, r, z=None, precision="fp64"):
+        z = self.empty() if z is None else z
+        L._check_vec(r, self.N, "r")
+        L._check_vec(z, self.N, "z")
+        L.rsfde_precond_apply(self.handle, r, z, precision)
+        return z
+
+    def step(self, u_prev, u_prev2, f_kind, opts, u_next=None, check=True):
+        u_next = self.empty() if u_next is None else u_next
+        L._check_vec(u_prev, self.N, "u_prev")
+        if u_prev2 is not None:
+            L._check_vec(u_prev2, self.N, "u_prev2")
+        L._check_vec(u_next, self.N, "u_next")
+        st = L.rsfde_step(self.handle, u_prev, u_prev2, f_kind, opts, u_next, check=check)
+        return u_next, StepStats(st.iters, st.restarts, st.relres, st.status)
+
+    def solve(self, b, x, opts, check=True):
+        L._check_vec(b, self.N, "b")
+        L._check_vec(x, self.N, "x")
+        st = L.rsfde_solve(self.handle, b, x, opts, check=check)
+        return x, StepStats(st.iters, st.restarts, st.relres, st.status)
+
+    def adjoint_step(self, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev, dk, mu=None):
+        for t, nm in ((u_prev, "u_prev"), (u_cur, "u_cur"), (lam_cur, "lam_cur"),
+                      (lam_prev, "lam_prev")):
+            L._check_vec(t, self.N, nm)
+        L._check_vec(dk, 2, "dk")
+        if mu is not None:
+            L._check_vec(mu, self.N, "mu")
+        st = L.rsfde_adjoint_step(self.handle, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev,
+                                  mu, dk)
+        return StepStats(st.iters, st.restarts, st.relres, st.status)
+
+    def march(self, u0, m, f_kind, opts, keep: Optional[List[int]] = None):
+        """Run m implicit steps from u0 (flat FP64 tensor).  Returns (u^m, iters per
+        step, {k: u^k for k in keep})."""
+        L._check_vec(u0, self.N, "u0")
+        bufs = [u0.clone(), self.empty(), self.empty()]
+        cur, prev = 0, None
+        iters = []
+        saved = {}
+        if keep and 0 in keep:
+            saved[0] = u0.clone()
+        for k in range(1, m + 1):
+            nxt = [i for i in range(3) if i != cur and i != prev][0]
+            _, st = self.step(bufs[cur], None if prev is None else bufs[prev], f_kind, opts,
+                              bufs[nxt])
+            iters.append(st.iters)
+            prev, cur = cur, nxt
+            if keep and k in keep:
+                saved[k] = bufs[cur].clone()
+        return bufs[cur], iters, saved

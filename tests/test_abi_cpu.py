@@ -1,0 +1,92 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/rsfde.h, and rejects bad arguments before touching a GPU."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "rsfde.h")
+LIB = os.path.join(ROOT, "paper_2102_11576_amd", "librsfde.so")
+
+
+def _declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsfde_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librsfde.so is not built (run __graft_entry__.build())")
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"rsfde_setup", "rsfde_matvec", "rsfde_precond_apply", "rsfde_step",
+            "rsfde_adjoint_step", "rsfde_destroy", "rsfde_strerror"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (rsfde_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_strerror(lib):
+    lib.rsfde_strerror.restype = C.c_char_p
+    assert lib.rsfde_strerror(0) == b"ok"
+    assert lib.rsfde_strerror(-1) == b"invalid argument"
+    assert lib.rsfde_strerror(-4).startswith(b"iteration cap")
+    assert lib.rsfde_strerror(12345) == b"unknown error"
+
+
+def test_host_validation_fails_fast(lib):
+    from paper_2102_11576_amd._lib import rsfde_grid, rsfde_solver_opts, rsfde_stats
+    P = C.c_void_p
+    lib.rsfde_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,
+                                C.c_double, C.c_double, P, C.c_double, C.c_double, C.c_int32, P]
+    h = P()
+    fake = P(0x1000)  # never dereferenced: validation rejects first
+    g = rsfde_grid(15, 15, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rsfde_setup(None, C.byref(g), 1.5, 1.5, 1.0, 1.0, fake, 1e-6, 0.1, 20, None) == -1
+    assert lib.rsfde_setup(C.byref(h), None, 1.5, 1.5, 1.0, 1.0, fake, 1e-6, 0.1, 20, None) == -1
+    for a1, a2, kx, ky, eta, dt in ((2.5, 1.5, 1, 1, 1e-6, .1), (1.5, 1.0, 1, 1, 1e-6, .1),
+                                    (1.5, 1.5, -1, 1, 1e-6, .1), (1.5, 1.5, 1, 1, 0.0, .1),
+                                    (1.5, 1.5, 1, 1, 1e-6, -0.1), (1.5, 1.5, 1, float("nan"), 1e-6, .1)):
+        assert lib.rsfde_setup(C.byref(h), C.byref(g), a1, a2, kx, ky, fake, eta, dt, 20, None) == -1
+        assert h.value is None
+    bad = rsfde_grid(0, 15, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rsfde_setup(C.byref(h), C.byref(bad), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 20, None) == -1
+    flip = rsfde_grid(15, 15, 1.0, 0.0, 0.0, 1.0)
+    assert lib.rsfde_setup(C.byref(h), C.byref(flip), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 20, None) == -1
+    assert lib.rsfde_setup(C.byref(h), C.byref(g), 1.5, 1.5, 1, 1, None, 1e-6, .1, 20, None) == -1
+    assert lib.rsfde_setup(C.byref(h), C.byref(g), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 65, None) == -1
+    big = rsfde_grid(8192, 15, 0.0, 1.0, 0.0, 1.0)
+    assert lib.rsfde_setup(C.byref(h), C.byref(big), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 20, None) == -7
+    # calls on a NULL plan
+    lib.rsfde_matvec.argtypes = [P, P, P, P]
+    assert lib.rsfde_matvec(None, fake, fake, None) == -1
+    lib.rsfde_set_coeffs.argtypes = [P, C.c_double, C.c_double]
+    assert lib.rsfde_set_coeffs(None, 1.0, 1.0) == -1
+    lib.rsfde_precond_apply.argtypes = [P, P, P, C.c_int32, P]
+    assert lib.rsfde_precond_apply(None, fake, fake, 0, None) == -1
+    st = rsfde_stats()
+    o = rsfde_solver_opts(20, 100, 1e-8, 0, 0)
+    lib.rsfde_step.argtypes = [P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P,
+                               C.POINTER(rsfde_stats), P]
+    assert lib.rsfde_step(None, fake, None, 1, C.byref(o), fake, C.byref(st), None) == -1
+    assert st.status == -1
+    lib.rsfde_destroy.argtypes = [P]
+    assert lib.rsfde_destroy(None) == 0
+
+
+def test_fft_engine_selftest():
+    from paper_2102_11576_amd.build import build_selftest
+    exe = build_selftest()
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout

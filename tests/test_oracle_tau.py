@@ -85,3 +85,16 @@ def test_lemma_4_4_and_4_5_spectra(name):
     assert ev.min() > 0.5 and ev.max() < 1.5
     ev2 = np.linalg.eigvals(np.linalg.solve(O.P_dense(p), O.dense_M(p))).real
     assert ev2.min() > 0.5 and ev2.max() < 1.5
+
+
+@pytest.mark.parametrize("name,n", [("c1", 9), ("c3", 16), ("c2", 5)])
+def test_fast_variants_equal_dense_forms(name, n):
+    p = _small_problem(name, n)
+    p.n2 = p.n1  # square
+    rng = np.random.default_rng(11)
+    V = rng.standard_normal((p.n2, p.n1))
+    assert np.allclose(O.precond_apply_fft(p, V), O.precond_apply(p, V), rtol=1e-12, atol=1e-14)
+    ref = O.matvec(p, V)
+    assert np.allclose(O.matvec_fast(p, V), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    for (j, i) in ((0, 0), (n - 1, 0), (n // 2, n // 3), (n - 1, n - 1)):
+        assert O.matvec_entry(p, V, j, i) == pytest.approx(ref[j, i], rel=1e-12, abs=1e-12 * np.abs(ref).max())
