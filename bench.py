@@ -1,0 +1,235 @@
+#!/usr/bin/env python
+"""Throughput of the tau-preconditioned GMRES time march on one MI355X.
+
+Workload (default): the 2047^2 rotated-ellipse configuration — alpha1 = alpha2
+= 1.9, kx = ky = 1, eta = 1e-6, 32 implicit steps to T = 1, f(u) = sin u,
+seeded 8-bump u0, flexible GMRES(30) to ||b - Mx|| <= 1e-8 ||b||.  A "step" is
+one implicit time step: right-hand side, initial guess and the full Krylov
+solve (preconditioner, matvec, Arnoldi, Givens, update, true residual).
+
+Prints one JSON line: unknown*timesteps/s of the FP64 path (inputs resident in
+HBM), GMRES iterations, the FP32-preconditioner variant and its error against
+the FP64 result, the HBM roofline of the dominant kernel (HIP events on the
+library's stream, algorithmic bytes) and the CPU oracle timed on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "unknown·timesteps/s at 2047², mixed vs FP64 at 1e-8 rel err; adjoint grads/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed implicit steps (default: all 32)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--mode", choices=["march", "kernels"], default="march",
+                    help="kernels: repeat each operator in isolation (for counter profiles)")
+    ap.add_argument("--reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def kernel_mode(args):
+    """Each operator in isolation at the workload's shape, for rocprofv3 runs:
+    a 256 MiB device copy (counter calibration: FETCH_SIZE and WRITE_SIZE of a
+    copy of known size), then --reps applications of the matvec, of the FP64
+    and FP32 preconditioner, and two implicit steps (Krylov kernels)."""
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from workloads.configs import make_config
+    w = make_config(args.workload, n=args.n)
+    dev = torch.device("cuda:0")
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x 256 MiB device-to-device copies")
+    plan = RsfdePlan.from_workload(w, device=dev)
+    u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+    y = plan.empty()
+    for _ in range(args.reps):
+        plan.matvec(u0, y)
+    torch.cuda.synchronize()
+    log(f"matvec x{args.reps}")
+    for prec in ("fp64", "fp32"):
+        for _ in range(args.reps):
+            plan.precond(u0, y, prec)
+        torch.cuda.synchronize()
+        log(f"precond {prec} x{args.reps}")
+    plan.march(u0, 2, w.f_kind, make_opts(w.restart, 100000, w.tol))
+    torch.cuda.synchronize()
+    log("2 implicit steps")
+    plan.close()
+
+
+def cpu_baseline(w, gpu_iters_per_step):
+    """The oracle as it stands (dense-free O2 operators: scipy FFT Toeplitz
+    products and DST-I, MGS GMRES) on a bounded sample of the same workload:
+    the first 2 and the first 8 inner iterations of step 1.  The difference
+    gives the cost of one inner iteration; the 2-iteration run minus two
+    iterations gives the fixed per-step cost (right-hand side, residuals,
+    update).  Scaled to unknown*timesteps/s with the GPU run's mean iterations
+    per step (same algorithm and stopping rule)."""
+    import numpy as np
+    import oracle as O
+
+    p = O.problem_from_workload(w)
+    lam = O.tau_eigs_xy(p)
+    A = lambda V: O.matvec_fast(p, V)  # noqa: E731
+    Pi = lambda V: O.precond_apply_fft(p, V, lam)  # noqa: E731
+    times = {}
+    for k in (2, 8):
+        t0 = time.perf_counter()
+        b = O.rhs(p, w.u0, w.f_kind)
+        O.gmres(A, b, w.u0, w.restart, w.tol, k, Pi, "right")
+        times[k] = time.perf_counter() - t0
+    t_it = (times[8] - times[2]) / 6.0
+    fixed = max(times[2] - 2 * t_it, 0.0)
+    t_step = fixed + gpu_iters_per_step * t_it
+    cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        cores = max(int(blas), 1) if blas else cores
+    except Exception:
+        pass
+    return {
+        "value": w.N / t_step,
+        "unit": "unknown·timesteps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"step 1 of the same {w.n1}x{w.n2} workload: oracle GMRES (scipy FFT Toeplitz "
+                   f"matvec, scipy DST-I preconditioner, MGS) for 2 and 8 inner iterations "
+                   f"({times[2]:.1f}s, {times[8]:.1f}s): {t_it:.3f}s/iteration + {fixed:.2f}s/step, "
+                   f"scaled by {gpu_iters_per_step:.1f} iterations/step"),
+    }
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.mode == "kernels":
+        kernel_mode(args)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
+                                   "design-only (see DESIGN.md). Use --gpus 1."}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from paper_2102_11576_amd import _lib as L
+    from workloads.configs import make_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = make_config(args.workload, n=args.n)
+    K = w.m if args.steps is None else args.steps
+    W = args.warmup
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    plan = RsfdePlan.from_workload(w, device=dev)
+    u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+
+    def timed_march(precision, steps, profile=False):
+        opts = make_opts(w.restart, 100000, w.tol, precision)
+        if W > 0:
+            plan.march(u0, min(W, w.m), w.f_kind, opts)
+        torch.cuda.synchronize()
+        if profile:
+            L.rsfde_profile(plan.handle, True)
+            L.rsfde_profile_read(plan.handle)
+        t0 = time.perf_counter()
+        u, iters, _ = plan.march(u0, steps, w.f_kind, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = L.rsfde_profile_read(plan.handle)
+            L.rsfde_profile(plan.handle, False)
+        return u, iters, dt, prof
+
+    log(f"workload {w.name} {w.n1}x{w.n2}, timing {K} steps after {W} warm-up steps")
+    u64, it64, t64, _ = timed_march("fp64", K)
+    value = w.N * K / t64
+    log(f"fp64: {1e3 * t64 / K:.2f} ms/step, {np.mean(it64):.1f} iterations/step")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknown·timesteps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * t64 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: {w.n1}x{w.n2} grid, rotated ellipse 0.45/0.25 at 30 deg in [0,1]^2, "
+                         f"alpha=({w.alpha1},{w.alpha2}), k=({w.kx},{w.ky}), eta={w.eta}, {w.m} steps "
+                         f"to T={w.T}, f=sin(u), 8 seeded Gaussian bumps, FGMRES({w.restart}) tol {w.tol}"),
+            "n1": w.n1, "n2": w.n2, "time_steps_total": w.m, "restart": w.restart, "tol": w.tol,
+            "preconditioner": "fp64",
+        },
+        "gmres_iters_per_step": float(np.mean(it64)),
+        "gmres_iters": it64,
+    }
+
+    if not args.no_mixed:
+        u32, it32, t32, _ = timed_march("fp32", K)
+        log(f"fp32 preconditioner: {1e3 * t32 / K:.2f} ms/step, {np.mean(it32):.1f} iterations/step")
+        d = float((u32 - u64).abs().max() / u64.abs().max())
+        out["mixed"] = {
+            "fp32": {"value": w.N * K / t32, "ms_per_step": 1e3 * t32 / K,
+                     "gmres_iters_per_step": float(np.mean(it32)), "rel_err_inf_vs_fp64": d},
+            "bf16": "not built in this version",
+        }
+
+    if not args.no_profile:
+        _, _, tprof, prof = timed_march("fp64", K, profile=True)
+        log(f"profiled run: {1e3 * tprof / K:.2f} ms/step")
+        kernels = {}
+        for name, (n, ms, by) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+            kernels[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n,
+                             "achieved_GBs": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                             "hbm_frac": (by / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS if ms > 0 else None}
+        dom = max(prof.items(), key=lambda kv: kv[1][1])
+        name, (n, ms, by) = dom
+        ach = by / (ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch_avg": by / n, "avg_launch_us": 1e3 * ms / n}
+        out["kernels"] = kernels
+        out["profiled_ms_per_step"] = 1e3 * tprof / K
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(w, float(np.mean(it64)))
+
+    plan.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

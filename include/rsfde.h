@@ -158,6 +158,23 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
                        double* lam_prev, double* mu_guess, double* dk_dev, rsfde_stats* stats,
                        void* stream);
 
+/* Kernel timing (measurement support, not part of the method).
+ * rsfde_profile(plan, 1) starts bracketing every kernel the plan launches with
+ * a pair of HIP events on the launch stream, tagged with the kernel family and
+ * its algorithmic byte count (each operand read once, each result written
+ * once); rsfde_profile(plan, 0) stops.  rsfde_profile_read waits for the
+ * recorded events, fills up to max entries (one per family seen since the
+ * last read), sets *count and clears the record.  Errors: EINVAL, EHIP. */
+typedef struct {
+  char name[24];       /* kernel family, e.g. "multidot", "mv_cols" */
+  int64_t launches;    /* launches recorded */
+  double total_ms;     /* sum of event-measured durations */
+  double bytes;        /* sum of algorithmic bytes of those launches */
+} rsfde_kernel_profile;
+
+int rsfde_profile(rsfde_plan plan, int32_t enable);
+int rsfde_profile_read(rsfde_plan plan, rsfde_kernel_profile* out, int32_t max, int32_t* count);
+
 /* Release the plan and all of its memory.  NULL is accepted. */
 int rsfde_destroy(rsfde_plan plan);
 

@@ -46,6 +46,11 @@ class rsfde_stats(C.Structure):
                 ("reserved", C.c_int32), ("relres", C.c_double), ("bnorm", C.c_double)]
 
 
+class rsfde_kernel_profile(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
 class RsfdeError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -68,11 +73,15 @@ def _load():
     lib.rsfde_solve.argtypes = [P, P, P, C.POINTER(rsfde_solver_opts), C.POINTER(rsfde_stats), P]
     lib.rsfde_adjoint_step.argtypes = [P, P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P, P,
                                        P, C.POINTER(rsfde_stats), P]
+    lib.rsfde_profile.argtypes = [P, C.c_int32]
+    lib.rsfde_profile_read.argtypes = [P, C.POINTER(rsfde_kernel_profile), C.c_int32,
+                                       C.POINTER(C.c_int32)]
     lib.rsfde_destroy.argtypes = [P]
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
     for f in ("rsfde_setup", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
-              "rsfde_step", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy"):
+              "rsfde_step", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy",
+              "rsfde_profile", "rsfde_profile_read"):
         getattr(lib, f).restype = C.c_int
     return lib
 
@@ -181,3 +190,16 @@ def rsfde_adjoint_step(plan, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev, mu_
 
 def rsfde_destroy(plan):
     _raise(_lib.rsfde_destroy(plan), "rsfde_destroy")
+
+
+def rsfde_profile(plan, enable):
+    _raise(_lib.rsfde_profile(plan, 1 if enable else 0), "rsfde_profile")
+
+
+def rsfde_profile_read(plan):
+    """{family: (launches, total_ms, algorithmic_bytes)} since the last read."""
+    buf = (rsfde_kernel_profile * 32)()
+    n = C.c_int32(0)
+    _raise(_lib.rsfde_profile_read(plan, buf, 32, C.byref(n)), "rsfde_profile_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
+            for i in range(n.value)}

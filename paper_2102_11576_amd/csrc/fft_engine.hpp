@@ -195,6 +195,39 @@ RS_HD int fft_slot_pos(int L, int P, int c) {
   return (c / h) * R + (c % h);
 }
 
+// x[q] *= w^q for q = 1..R-1, with w^q built from the one loaded root w by
+// squarings and products (at most five roundings deep for R = 16) instead of
+// R-1 table loads: fewer live registers and one memory latency per butterfly.
+template <typename T, int R>
+RS_HD void apply_twiddles(cpx<T>* x, cpx<T> w1) {
+  if constexpr (R >= 2) x[1] = cmul(x[1], w1);
+  if constexpr (R >= 4) {
+    const cpx<T> w2 = cmul(w1, w1);
+    const cpx<T> w3 = cmul(w2, w1);
+    x[2] = cmul(x[2], w2);
+    x[3] = cmul(x[3], w3);
+    if constexpr (R >= 8) {
+      const cpx<T> w4 = cmul(w2, w2);
+      x[4] = cmul(x[4], w4);
+      x[5] = cmul(x[5], cmul(w4, w1));
+      x[6] = cmul(x[6], cmul(w4, w2));
+      x[7] = cmul(x[7], cmul(w4, w3));
+      if constexpr (R >= 16) {
+        const cpx<T> w8 = cmul(w4, w4);
+        x[8] = cmul(x[8], w8);
+        x[9] = cmul(x[9], cmul(w8, w1));
+        x[10] = cmul(x[10], cmul(w8, w2));
+        x[11] = cmul(x[11], cmul(w8, w3));
+        const cpx<T> w12 = cmul(w8, w4);
+        x[12] = cmul(x[12], w12);
+        x[13] = cmul(x[13], cmul(w12, w1));
+        x[14] = cmul(x[14], cmul(w12, w2));
+        x[15] = cmul(x[15], cmul(w12, w3));
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-thread stage kernels.  `tw` is the table exp(-2 pi i j / L), j < L.
 // ---------------------------------------------------------------------------
@@ -231,10 +264,7 @@ struct Fft {
       Dft<T, R, -1>::run(reg + u * R);
       if constexpr (t < NS - 1) {
         const int k = (tau + u * TPF) % s;
-        static_for<R - 1>([&](auto qq) {
-          constexpr int q = decltype(qq)::value + 1;
-          reg[u * R + q] = cmul(reg[u * R + q], tw[(k * q) << twsh]);
-        });
+        apply_twiddles<T, R>(reg + u * R, tw[k << twsh]);
       }
     });
   }
@@ -249,13 +279,10 @@ struct Fft {
       constexpr int u = decltype(uu)::value;
       if constexpr (t < NS - 1) {
         const int k = (tau + u * TPF) % s;
-        static_for<R - 1>([&](auto qq) {
-          constexpr int q = decltype(qq)::value + 1;
-          // exp(+2 pi i j / L) = tw[L - j]: indexing the mirrored entry (instead of
-          // conjugating tw[j]) keeps the compiler from holding every forward
-          // twiddle in registers until the inverse sweep.
-          reg[u * R + q] = cmul(reg[u * R + q], tw[(L - ((k * q) << twsh)) & (L - 1)]);
-        });
+        // exp(+2 pi i k / L_t) = tw[L - (k << twsh)]: indexing the mirrored entry
+        // (instead of conjugating tw[k]) keeps the compiler from holding the
+        // forward twiddles in registers until the inverse sweep.
+        apply_twiddles<T, R>(reg + u * R, tw[(L - (k << twsh)) & (L - 1)]);
       }
       Dft<T, R, +1>::run(reg + u * R);
     });

@@ -11,7 +11,7 @@ namespace rsfde {
 
 constexpr int kMaxRestart = 64;       // largest GMRES restart length supported
 constexpr int kRedThreads = 256;      // threads per block of the streaming reductions
-constexpr int kMaxRedBlocks = 2048;   // upper bound on blocks of a streaming reduction
+constexpr int kMaxRedBlocks = 1024;   // upper bound on blocks of a streaming reduction
 constexpr int kMinLog2L = 1;          // FFT lengths 2 .. 16384
 constexpr int kMaxLog2L = 14;
 
@@ -19,7 +19,7 @@ constexpr int kMaxLog2L = 14;
 constexpr int fft_pts(int L) { return L < 16 ? L : (L >= 8192 ? 8 : 16); }
 // Pass B of the preconditioner keeps half a spectrum in registers besides the
 // FFT data, so it runs radix-8.
-constexpr int pc_cols_pts(int L) { return L < 8 ? L : 8; }
+constexpr int pc_cols_pts(int L) { return L < 16 ? L : (L >= 16384 ? 8 : 16); }
 
 // Values the device writes for the host after each Arnoldi step.  Lives in
 // pinned, device-visible host memory; the host reads it after an event.
@@ -42,10 +42,10 @@ struct KrylovState {
 };
 constexpr int kLdH = kMaxRestart + 1;
 
-// Reduction workspace: partial sums and the "last block" ticket counters.
+// Reduction workspace: per-block partial sums [value][block], read by the
+// single-block finishing kernel launched after each streaming kernel.
 struct RedWork {
   double* partial;     // [kMaxRestart + 2][kMaxRedBlocks]
-  unsigned* counters;  // [16]
 };
 
 // ----------------------------- FFT kernels --------------------------------

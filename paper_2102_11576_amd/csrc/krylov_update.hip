@@ -1,0 +1,75 @@
+// Solution update at the end of a restart cycle of the flexible GMRES:
+// x += sum_{i<jc} y_i Z_i with R y = g (R = the rotated, upper-triangular
+// Hessenberg matrix).  Every block solves the small triangular system itself.
+#include "krylov_common.hpp"
+
+namespace rsfde {
+
+template <int NV>
+__global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict__ Z, size_t ldz,
+                                                        double* __restrict__ x, size_t N,
+                                                        const KrylovState* __restrict__ ks,
+                                                        int v0, int jc) {
+  __shared__ double y[kMaxRestart];
+  if (threadIdx.x == 0) {
+    for (int i = jc - 1; i >= 0; --i) {
+      double s = ks->g[i];
+      for (int k = i + 1; k < jc; ++k) s -= ks->H[(size_t)k * kLdH + i] * y[k];
+      const double d = ks->H[(size_t)i * kLdH + i];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+  __syncthreads();
+  double c[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v];
+  const size_t N2 = N / 2;
+  double2* x2 = reinterpret_cast<double2*>(x);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double2 z[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) z[v] = reinterpret_cast<const double2*>(Z + (size_t)v * ldz)[i];
+    double2 s = x2[i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      s.x += c[v] * z[v].x;
+      s.y += c[v] * z[v].y;
+    }
+    x2[i] = s;
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = x[N - 1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s += c[v] * Z[(size_t)v * ldz + N - 1];
+    x[N - 1] = s;
+  }
+}
+
+using UpdateFn = void (*)(const double*, size_t, double*, size_t, const KrylovState*, int, int,
+                          dim3, hipStream_t);
+template <int NV>
+static void run_update(const double* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
+                       int v0, int jc, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc);
+}
+template <int... I>
+static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
+  return {&run_update<I + 1>...};
+}
+static const auto kUpdate = update_table(std::make_integer_sequence<int, kChunk>{});
+
+hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
+                         KrylovState* ks, hipStream_t s) {
+  if (jc <= 0) return hipSuccess;
+  if (jc > kMaxRestart) return hipErrorInvalidValue;
+  for (int v0 = 0; v0 < jc; v0 += kChunk) {
+    const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, dim3(red_blocks(N)), s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace rsfde

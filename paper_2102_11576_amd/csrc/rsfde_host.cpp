@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <new>
 #include <vector>
@@ -92,17 +93,42 @@ struct Plan {
   int* mirror = nullptr;
   std::map<int, void*> tw64, tw32;
   KrylovState* ks = nullptr;
-  RedWork rw{nullptr, nullptr};
+  RedWork rw{nullptr};
   HostStatus* hs = nullptr;      // pinned host memory
   HostStatus* hs_dev = nullptr;  // its device-visible address
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<void*> allocs;
+
+  // kernel timing (rsfde_profile)
+  struct ProfRec {
+    int cat;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
 
   ~Plan() {
     for (void* p : allocs) (void)hipFree(p);
     if (hs) (void)hipHostFree(hs);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& r : prof_recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
   }
 
   template <typename T>
@@ -119,6 +145,34 @@ struct Plan {
 namespace {
 
 hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
+
+enum ProfCat {
+  kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
+  kCatUpdate, kCatResidual, kCatRhs, kCatOther, kNumCats
+};
+const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
+                                         "pc_rows_inv", "multidot", "axpy_givens", "update",
+                                         "residual", "rhs", "other"};
+
+// Brackets one kernel launch with timing events when profiling is on.
+struct ProfScope {
+  Plan* P;
+  hipStream_t s;
+  int cat;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(Plan* P_, hipStream_t s_, int cat_, double bytes_) : P(P_), s(s_), cat(cat_), bytes(bytes_) {
+    if (P->prof_on) {
+      a = P->take_event();
+      if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = P->take_event();
+    if (b && hipEventRecord(b, s) == hipSuccess) P->prof_recs.push_back({cat, a, b, bytes});
+  }
+};
 
 // First column of the unit-coefficient Toeplitz matrix c * G_n^(alpha) (G).
 std::vector<double> toeplitz_col(double alpha, int n, double c) {
@@ -200,9 +254,16 @@ hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
 }
 
 int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s) {
-  CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
-                    P->dpen, 0, s));
-  CK(launch_mv_cols(P->Lcy, x, P->t, y, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+  const double N = (double)P->N;
+  {
+    ProfScope ps(P, s, kCatMvRows, 17.0 * N);
+    CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
+                      P->dpen, 0, s));
+  }
+  {
+    ProfScope ps(P, s, kCatMvCols, 24.0 * N);
+    CK(launch_mv_cols(P->Lcy, x, P->t, y, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+  }
   return RSFDE_OK;
 }
 
@@ -210,22 +271,41 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
                  hipStream_t s) {
   if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
   const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
+  const double N = (double)P->N, S = (double)(P->n1 + 1) * (double)P->n2;
   if (precision == RSFDE_FP64) {
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
-    CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
-    CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
-                              P->n2, P->kx, P->ky, P->dpen, Kfac, s));
-    CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw64[P->Ldx], P->n1,
-                                  P->n2, s));
+    {
+      ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
+      CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcCols, 24.0 * S);
+      CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcRowsInv, 16.0 * S + 9.0 * N);
+      CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw64[P->Ldx],
+                                    P->n1, P->n2, s));
+    }
     return RSFDE_OK;
   }
   if (precision == RSFDE_FP32) {
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
-    CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
-    CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
-                             P->n2, P->kx, P->ky, P->dpen, Kfac, s));
-    CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw32[P->Ldx], P->n1,
-                                 P->n2, s));
+    {
+      ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
+      CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcCols, 12.0 * S);
+      CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcRowsInv, 8.0 * S + 9.0 * N);
+      CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw32[P->Ldx],
+                                   P->n1, P->n2, s));
+    }
     return RSFDE_OK;
   }
   return RSFDE_EUNSUPPORTED;
@@ -279,7 +359,10 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
   for (;;) {
     int rc = matvec_impl(P, x, P->w, s);
     if (rc) return finish(st, rc, total, cycles, beta, bnorm);
-    CK(launch_residual(P->b, P->w, P->V, N, P->rw, P->ks, P->hs_dev, s));
+    {
+      ProfScope ps(P, s, kCatResidual, 24.0 * N);
+      CK(launch_residual(P->b, P->w, P->V, N, P->rw, P->ks, P->hs_dev, s));
+    }
     CK(hipStreamSynchronize(s));
     if (vread(&hs->flags) & kFlagNonFinite) return finish(st, RSFDE_ENONFINITE, total, cycles, beta, bnorm);
     beta = vread(&hs->beta);
@@ -296,13 +379,20 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
         rc = precond_impl(P, vj, sig, zj, o->precision, s);
         if (rc) return finish(st, rc, total, cycles, beta, bnorm);
       } else {
+        ProfScope ps(P, s, kCatOther, 16.0 * N);
         CK(launch_scale_copy(vj, sig, zj, N, s));
       }
       rc = matvec_impl(P, zj, P->w, s);
       if (rc) return finish(st, rc, total, cycles, beta, bnorm);
-      CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, s));
-      CK(launch_axpy_givens(P->V, ld, j + 1, P->w, P->V + (size_t)(j + 1) * ld, N, P->rw, P->ks,
-                            j, P->hs_dev, s));
+      {
+        ProfScope ps(P, s, kCatMultidot, 8.0 * (j + 2) * (double)N);
+        CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, s));
+      }
+      {
+        ProfScope ps(P, s, kCatAxpy, 8.0 * (j + 3) * (double)N);
+        CK(launch_axpy_givens(P->V, ld, j + 1, P->w, P->V + (size_t)(j + 1) * ld, N, P->rw,
+                              P->ks, j, P->hs_dev, s));
+      }
       CK(hipEventRecord(P->ev[j & 1], s));
       // Look one iteration behind: the device runs step j while the host
       // checks step j-1.  A converged j-1 leaves step j's work unused
@@ -323,7 +413,10 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
         return finish(st, RSFDE_ENONFINITE, total + jmax, cycles, beta, bnorm);
       jc = jmax;
     }
-    CK(launch_update(P->Z, ld, jc, x, N, P->ks, s));
+    {
+      ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
+      CK(launch_update(P->Z, ld, jc, x, N, P->ks, s));
+    }
     total += jc;
   }
 }
@@ -434,7 +527,6 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   P->P2 = q;
   AL(P->ks, 1);
   AL(P->rw.partial, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
-  AL(P->rw.counters, 16);
 #undef AL
   if (hipHostMalloc((void**)&P->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
       hipSuccess)
@@ -445,7 +537,6 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RSFDE_EHIP);
 
   if (hipMemcpyAsync(P->mask, mask_dev, N, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(RSFDE_EHIP);
-  if (hipMemsetAsync(P->rw.counters, 0, 16 * sizeof(unsigned), s) != hipSuccess) return fail(RSFDE_EHIP);
   if (hipMemsetAsync(P->ks, 0, sizeof(KrylovState), s) != hipSuccess) return fail(RSFDE_EHIP);
 
   // Matrix-vector symbols (unit kx, ky).
@@ -528,9 +619,12 @@ int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int
   if (!g.ok) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   hipStream_t s = pick(P, stream);
   P->hs->flags = 0;
-  if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, P->b, u_next, P->N, P->rw, P->hs_dev, s) !=
-      hipSuccess)
-    return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  {
+    ProfScope ps(P, s, kCatRhs, (u_prev2 ? 33.0 : 25.0) * (double)P->N);
+    if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, P->b, u_next, P->N, P->rw, P->hs_dev,
+                   s) != hipSuccess)
+      return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  }
   return solve_core(P, u_next, opts, stats, s);
 }
 
@@ -586,6 +680,48 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
     return finish(stats, RSFDE_EHIP, stats ? stats->iters : 0, 0, 0, 0);
   if (hipStreamSynchronize(s) != hipSuccess) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   return RSFDE_OK;
+}
+
+int rsfde_profile(rsfde_plan plan, int32_t enable) {
+  if (!plan) return RSFDE_EINVAL;
+  plan->p.prof_on = enable != 0;
+  return RSFDE_OK;
+}
+
+int rsfde_profile_read(rsfde_plan plan, rsfde_kernel_profile* out, int32_t max, int32_t* count) {
+  using namespace rsfde;
+  if (!plan || !count || (max > 0 && !out) || max < 0) return RSFDE_EINVAL;
+  Plan* P = &plan->p;
+  DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  int64_t launches[kNumCats] = {0};
+  double ms[kNumCats] = {0}, bytes[kNumCats] = {0};
+  int rc = RSFDE_OK;
+  for (auto& r : P->prof_recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      rc = RSFDE_EHIP;
+    launches[r.cat] += 1;
+    ms[r.cat] += t;
+    bytes[r.cat] += r.bytes;
+    P->ev_pool.push_back(r.a);
+    P->ev_pool.push_back(r.b);
+  }
+  P->prof_recs.clear();
+  int n = 0;
+  for (int c = 0; c < kNumCats; ++c) {
+    if (!launches[c]) continue;
+    if (n < max) {
+      std::memset(&out[n], 0, sizeof(rsfde_kernel_profile));
+      std::strncpy(out[n].name, kCatNames[c], sizeof(out[n].name) - 1);
+      out[n].launches = launches[c];
+      out[n].total_ms = ms[c];
+      out[n].bytes = bytes[c];
+    }
+    ++n;
+  }
+  *count = n < max ? n : max;
+  return rc;
 }
 
 int rsfde_destroy(rsfde_plan plan) {

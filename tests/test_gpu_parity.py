@@ -166,3 +166,18 @@ def test_all_inside_and_all_outside_masks():
             u, _, _ = pl.march(_t(w.u0), w.m, w.f_kind, make_opts(20, 1000, 1e-12))
         err = np.abs(u.cpu().numpy().reshape(15, 15) - ref).max() / np.abs(ref).max()
         assert err <= 1e-10, (val, err)
+
+
+@pytest.mark.parametrize("restart", [1, 5, 33, 40, 64])
+def test_long_and_short_restarts(restart):
+    """Restart lengths beyond one 32-vector chunk (split multi-dot / axpy / update)
+    and degenerate GMRES(1) agree with LU."""
+    w = make_config("c3", n=31, m=2)
+    p = O.problem_from_workload(w)
+    ref = O.march_lu(p, w.u0, w.m, w.f_kind)
+    with RsfdePlan.from_workload(w, max_restart=restart) as pl:
+        u, iters, _ = pl.march(_t(w.u0), w.m, w.f_kind, make_opts(restart, 100000, 1e-12,
+                                                                   precond="none"))
+        u = u.cpu().numpy().reshape(w.n2, w.n1)
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    assert err <= 1e-10, (restart, err, iters)
