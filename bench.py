@@ -200,11 +200,26 @@ def main():
         u32, it32, t32, _ = timed_march("fp32", K)
         log(f"fp32 preconditioner: {1e3 * t32 / K:.2f} ms/step, {np.mean(it32):.1f} iterations/step")
         d = float((u32 - u64).abs().max() / u64.abs().max())
+        ub, itb, tb, profb = timed_march("bf16", K, profile=not args.no_profile)
+        log(f"bf16 preconditioner: {1e3 * tb / K:.2f} ms/step, {np.mean(itb):.1f} iterations/step")
+        db = float((ub - u64).abs().max() / u64.abs().max())
         out["mixed"] = {
             "fp32": {"value": w.N * K / t32, "ms_per_step": 1e3 * t32 / K,
                      "gmres_iters_per_step": float(np.mean(it32)), "rel_err_inf_vs_fp64": d},
-            "bf16": "not built in this version",
+            "bf16": {"value": w.N * K / tb, "ms_per_step": 1e3 * tb / K,
+                     "gmres_iters_per_step": float(np.mean(itb)), "rel_err_inf_vs_fp64": db},
         }
+        if profb and "pc_gemm_bf16" in profb:
+            n_l, ms_l, _ = profb["pc_gemm_bf16"]
+            n1p, n2p = (w.n1 + 127) // 128 * 128, (w.n2 + 127) // 128 * 128
+            # forward products with split (3 MFMA) operands: 2*3*n1p*n2p*(n1p + n2p); inverse
+            # products: 2*2*n1p*n2p*(n1p + n2p)  (20 n^3 per apply for n1 = n2)
+            flops = 10.0 * n1p * n2p * (n1p + n2p)
+            tfs = flops / (ms_l / n_l * 1e-3) / 1e12
+            out["mixed"]["bf16"]["mfma_roofline"] = {
+                "kernel": "pc_gemm_bf16", "bound": "mfma", "achieved": tfs, "peak": 2500.0,
+                "unit": "TFLOP/s", "frac": tfs / 2500.0, "avg_apply_us": 1e3 * ms_l / n_l,
+                "flops_per_apply": flops}
 
     if not args.no_profile:
         _, _, tprof, prof = timed_march("fp64", K, profile=True)

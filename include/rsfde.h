@@ -75,6 +75,9 @@ typedef struct {
   double tol;        /* stop when ||b - M x||_2 <= tol * ||b||_2 (tol > 0) */
   int32_t precision; /* RSFDE_FP64 / RSFDE_FP32 / RSFDE_BF16: preconditioner arithmetic */
   int32_t precond;   /* RSFDE_PRECOND_TAU or RSFDE_PRECOND_NONE */
+  int32_t reorth;    /* Gram-Schmidt passes: 1 = two (CGS2), -1 = one (CGS),
+                        0 = default: two with the BF16 preconditioner, else one */
+  int32_t reserved;
 } rsfde_solver_opts;
 
 typedef struct {
@@ -100,9 +103,10 @@ typedef struct {
  *   eta, dt     : penalty parameter > 0 and time step > 0
  *   max_restart : largest restart the plan will run (1..64; <= 0 means 30)
  *   stream      : stream for the set-up uploads
- * The sine-transform preconditioner requires n1+1 and n2+1 to be powers of
- * two (the FFT lengths 2(n+1)); other sizes support the matrix-vector product
- * and RSFDE_PRECOND_NONE only.  Sizes up to n = 8191 per direction.
+ * The FP64 / FP32 sine-transform preconditioner requires n1+1 and n2+1 to be
+ * powers of two (FFT lengths 2(n+1)); other sizes support the matrix-vector
+ * product, RSFDE_PRECOND_NONE and the BF16 preconditioner.  Sizes up to
+ * n = 8191 per direction.
  * Errors: EINVAL, ENOMEM, EHIP.
  */
 int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double alpha2,
@@ -120,8 +124,10 @@ int rsfde_matvec(rsfde_plan plan, const double* x, double* y, void* stream);
 
 /* z = P_hat^{-1} r (preconditioner): 2-D DST-I, the two eigenvalue scalings
  * 1/(1 - lx_i - ly_j) and 1/(1 + dt/eta - lx_i - ly_j), inverse 2-D DST-I,
- * combined by the mask.  precision selects the internal arithmetic (FP64,
- * FP32; BF16 returns EUNSUPPORTED in this build).  r and z must not overlap.
+ * combined by the mask.  precision selects the internal arithmetic: FP64 or
+ * FP32 run the transforms as FFTs (n1+1, n2+1 powers of two); BF16 runs them
+ * as dense sine-matrix products on the matrix cores (BF16 operands, FP32
+ * accumulation; any n).  r and z must not overlap.
  * Errors: EINVAL, EUNSUPPORTED, EHIP. */
 int rsfde_precond_apply(rsfde_plan plan, const double* r, double* z, int32_t precision,
                         void* stream);

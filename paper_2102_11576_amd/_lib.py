@@ -38,7 +38,8 @@ class rsfde_grid(C.Structure):
 
 class rsfde_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
-                ("precision", C.c_int32), ("precond", C.c_int32)]
+                ("precision", C.c_int32), ("precond", C.c_int32), ("reorth", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class rsfde_stats(C.Structure):
@@ -127,11 +128,12 @@ def _raise(rc, where):
         raise RsfdeError(rc, where)
 
 
-def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau"):
+def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0):
+    """reorth: 1 = two Gram-Schmidt passes, -1 = one, 0 = two only with BF16."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
         if isinstance(precond, str) else int(precond)
-    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc)
+    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), 0)
 
 
 def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30, stream=None):

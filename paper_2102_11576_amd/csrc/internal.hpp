@@ -39,6 +39,7 @@ struct KrylovState {
   double sn[kMaxRestart];
   double g[kMaxRestart + 1];
   double vscale[kMaxRestart + 1];             // V_i is stored unnormalised: v_i = vscale[i] * V_i
+  double h2[kMaxRestart + 1];                 // second Gram-Schmidt pass (reorthogonalisation)
 };
 constexpr int kLdH = kMaxRestart + 1;
 
@@ -78,17 +79,32 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
                               const uint8_t* mask, double* z, const void* tw,
                               int n1, int n2, hipStream_t s);
 
+// BF16 / MFMA form of the same preconditioner (dense sine-transform GEMMs,
+// any n; dimensions padded to multiples of 128).  A1T holds 2 n1p n2p values
+// (hi and lo parts of the split intermediate).
+hipError_t launch_pc_gemm_bf16(const double* v, const double* sig, double* z, const uint8_t* mask,
+                               const __bf16* Sx, const __bf16* Sy, const __bf16* Sx_lo,
+                               const __bf16* Sy_lo, const float* lamx,
+                               const float* lamy, __bf16* A1T, __bf16* R12T, __bf16* G,
+                               int n1, int n2, int n1p, int n2p, double kx, double ky,
+                               double dpen, hipStream_t s);
+
 // ---------------------------- Krylov kernels ------------------------------
 hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
                       int f_kind, double* b, double* x0, size_t N, RedWork rw,
                       HostStatus* hs, hipStream_t s);
 hipError_t launch_residual(const double* b, const double* w, double* r, size_t N,
                            RedWork rw, KrylovState* ks, HostStatus* hs, hipStream_t s);
+// h_i = <v_i, w>, i < nv, into column j of H (second = false) or into ks->h2
+// (second = true: the reorthogonalisation pass).
 hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w, size_t N,
-                           RedWork rw, KrylovState* ks, int j, hipStream_t s);
+                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s);
+// vout = w - sum_i c_i v_i with c = column j of H (second = false) or ks->h2;
+// finish = true also takes ||vout|| and does the Givens step (adding h2 into
+// column j first when second = true).
 hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w,
                               double* vout, size_t N, RedWork rw, KrylovState* ks, int j,
-                              HostStatus* hs, hipStream_t s);
+                              bool second, bool finish, HostStatus* hs, hipStream_t s);
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
                          KrylovState* ks, hipStream_t s);
 hipError_t launch_scale_copy(const double* v, const double* sig, double* z, size_t N,

@@ -12,12 +12,12 @@ template <int NV, bool FINAL>
 __global__ __launch_bounds__(kRedThreads) void k_axpy_givens(const double* __restrict__ V,
                                                              size_t ldv, const double* win,
                                                              double* vout, size_t N, RedWork rw,
-                                                             KrylovState* ks, int j, int v0,
-                                                             HostStatus* hs) {
+                                                             const double* coef, int v0,
+                                                             const double* vscale) {
   __shared__ double sh[16 * 1];
   double c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = ks->H[(size_t)j * kLdH + v0 + v] * ks->vscale[v0 + v];
+  for (int v = 0; v < NV; ++v) c[v] = coef[v0 + v] * vscale[v0 + v];
   double acc[1] = {0.0};
   const size_t N2 = N / 2;
   const double2* w2 = reinterpret_cast<const double2*>(win);
@@ -49,11 +49,13 @@ __global__ __launch_bounds__(kRedThreads) void k_axpy_givens(const double* __res
 // beta = ||V_{j+1}||, H[j+1][j] = beta, vscale[j+1] = 1/beta, the previous
 // Givens rotations applied to column j, rotation j, and |g_{j+1}| for the host.
 __global__ __launch_bounds__(kFinishThreads) void k_givens(RedWork rw, int nb, KrylovState* ks,
-                                                           int j, HostStatus* hs) {
+                                                           int j, int add_h2, HostStatus* hs) {
   if ((threadIdx.x >> 6) > 0) return;
   const double uu = wave_total(rw, 0, nb);
   if (threadIdx.x != 0) return;
   double* Hj = ks->H + (size_t)j * kLdH;
+  if (add_h2)
+    for (int i = 0; i <= j; ++i) Hj[i] += ks->h2[i];
   const double beta = sqrt(uu);
   Hj[j + 1] = beta;
   ks->vscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -79,14 +81,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_givens(RedWork rw, int nb, K
 }
 
 using AxpyFn = void (*)(const double*, size_t, const double*, double*, size_t, RedWork,
-                        KrylovState*, int, int, HostStatus*, dim3, hipStream_t);
+                        const double*, int, const double*, dim3, hipStream_t);
 
 template <int NV, bool FINAL>
 static void run_axpy(const double* V, size_t ldv, const double* win, double* vout, size_t N,
-                     RedWork rw, KrylovState* ks, int j, int v0, HostStatus* hs, dim3 g,
+                     RedWork rw, const double* coef, int v0, const double* vscale, dim3 g,
                      hipStream_t s) {
   hipLaunchKernelGGL((k_axpy_givens<NV, FINAL>), g, dim3(kRedThreads), 0, s, V, ldv, win, vout, N,
-                     rw, ks, j, v0, hs);
+                     rw, coef, v0, vscale);
 }
 template <bool FINAL, int... I>
 static constexpr std::array<AxpyFn, sizeof...(I)> axpy_table(std::integer_sequence<int, I...>) {
@@ -96,18 +98,20 @@ static const auto kAxpyFinal = axpy_table<true>(std::make_integer_sequence<int, 
 static const auto kAxpyPart = axpy_table<false>(std::make_integer_sequence<int, kChunk>{});
 
 hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w, double* vout,
-                              size_t N, RedWork rw, KrylovState* ks, int j, HostStatus* hs,
-                              hipStream_t s) {
+                              size_t N, RedWork rw, KrylovState* ks, int j, bool second,
+                              bool finish, HostStatus* hs, hipStream_t s) {
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  const double* coef = second ? ks->h2 : ks->H + (size_t)j * kLdH;
   for (int v0 = 0; v0 < nv; v0 += kChunk) {
     const int n = nv - v0 < kChunk ? nv - v0 : kChunk;
-    const bool last = v0 + n == nv;
+    const bool last = finish && v0 + n == nv;
     const double* win = v0 == 0 ? w : vout;
     const int nb = red_blocks(N);
-    (last ? kAxpyFinal : kAxpyPart)[n - 1](V + (size_t)v0 * ldv, ldv, win, vout, N, rw, ks, j, v0,
-                                           hs, dim3(nb), s);
+    (last ? kAxpyFinal : kAxpyPart)[n - 1](V + (size_t)v0 * ldv, ldv, win, vout, N, rw, coef, v0,
+                                           ks->vscale, dim3(nb), s);
     if (last)
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, ks, j, hs);
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, ks, j,
+                         second ? 1 : 0, hs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

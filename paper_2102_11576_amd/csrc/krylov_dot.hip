@@ -35,14 +35,15 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restri
   publish_partials<NV>(acc, NV, rw, sh);
 }
 
-// H[v0 + v][j] = vscale[v0 + v] * (sum of the partials of value v), v < nv.
+// dst[v0 + v] = vscale[v0 + v] * (sum of the partials of value v), v < nv;
+// dst is column j of H or the reorthogonalisation vector h2.
 __global__ __launch_bounds__(kFinishThreads) void k_multidot_finish(RedWork rw, int nb, int nv,
-                                                                    KrylovState* ks, int j,
+                                                                    KrylovState* ks, double* dst,
                                                                     int v0) {
   const int lane = threadIdx.x & 63;
   for (int v = threadIdx.x >> 6; v < nv; v += kFinishThreads / 64) {
     const double t = wave_total(rw, v, nb);
-    if (lane == 0) ks->H[(size_t)j * kLdH + v0 + v] = ks->vscale[v0 + v] * t;
+    if (lane == 0) dst[v0 + v] = ks->vscale[v0 + v] * t;
   }
 }
 
@@ -61,13 +62,14 @@ static constexpr std::array<MultidotFn, sizeof...(I)> multidot_table(std::intege
 static const auto kMultidot = multidot_table(std::make_integer_sequence<int, kChunk>{});
 
 hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w, size_t N,
-                           RedWork rw, KrylovState* ks, int j, hipStream_t s) {
+                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s) {
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  double* dst = second ? ks->h2 : ks->H + (size_t)j * kLdH;
   for (int v0 = 0; v0 < nv; v0 += kChunk) {
     const int n = nv - v0 < kChunk ? nv - v0 : kChunk;
     const int nb = red_blocks(N);
     kMultidot[n - 1](V + (size_t)v0 * ldv, ldv, w, N, rw, ks, j, v0, dim3(nb), s);
-    hipLaunchKernelGGL(k_multidot_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, n, ks, j,
+    hipLaunchKernelGGL(k_multidot_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, n, ks, dst,
                        v0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -92,6 +92,17 @@ struct Plan {
   float* lamy32 = nullptr;
   int* mirror = nullptr;
   std::map<int, void*> tw64, tw32;
+  // BF16 / MFMA preconditioner
+  int n1p = 0, n2p = 0;
+  __bf16* Sx16 = nullptr;
+  __bf16* Sy16 = nullptr;
+  __bf16* Sx16lo = nullptr;  // S - bf16(S), for the split forward products
+  __bf16* Sy16lo = nullptr;
+  float* lamx_nat = nullptr;
+  float* lamy_nat = nullptr;
+  __bf16* A1T = nullptr;
+  __bf16* R12T = nullptr;
+  __bf16* G = nullptr;
   KrylovState* ks = nullptr;
   RedWork rw{nullptr};
   HostStatus* hs = nullptr;      // pinned host memory
@@ -148,11 +159,11 @@ hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
 
 enum ProfCat {
   kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
-  kCatUpdate, kCatResidual, kCatRhs, kCatOther, kNumCats
+  kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kNumCats
 };
 const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
                                          "pc_rows_inv", "multidot", "axpy_givens", "update",
-                                         "residual", "rhs", "other"};
+                                         "residual", "rhs", "other", "pc_gemm_bf16"};
 
 // Brackets one kernel launch with timing events when profiling is on.
 struct ProfScope {
@@ -233,6 +244,40 @@ std::vector<T> twiddles(int L) {
   return tw;
 }
 
+// float -> bf16, round to nearest even (finite inputs).
+uint16_t to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+float from_bf16_bits(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Orthonormal DST-I matrix sqrt(2/(n+1)) sin(pi (i+1)(j+1)/(n+1)) (Section 4.1),
+// zero-padded to np x np, as BF16 bit patterns: hi = bf16(S), lo = bf16(S - hi).
+void sine_matrix_bf16(int n, int np, std::vector<uint16_t>& hi, std::vector<uint16_t>& lo) {
+  const int L = 2 * (n + 1);
+  std::vector<double> sn(L);
+  for (int m = 0; m < L; ++m) sn[m] = std::sin(kPi * (double)m / (double)(n + 1));
+  const double c = std::sqrt(2.0 / (n + 1));
+  hi.assign((size_t)np * np, 0);
+  lo.assign((size_t)np * np, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double v = c * sn[(int)(((long long)(i + 1) * (j + 1)) % L)];
+      const uint16_t h = to_bf16_bits((float)v);
+      hi[(size_t)i * np + j] = h;
+      lo[(size_t)i * np + j] = to_bf16_bits((float)(v - (double)from_bf16_bits(h)));
+    }
+}
+
 template <typename T>
 hipError_t upload(Plan* P, T** dst, const std::vector<T>& src, hipStream_t s) {
   hipError_t e = P->dalloc(dst, src.size());
@@ -269,6 +314,13 @@ int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s) {
 
 int precond_impl(Plan* P, const double* r, const double* sig, double* z, int precision,
                  hipStream_t s) {
+  if (precision == RSFDE_BF16) {
+    ProfScope ps(P, s, kCatPcGemm, 17.0 * (double)P->N);
+    CK(launch_pc_gemm_bf16(r, sig, z, P->mask, P->Sx16, P->Sy16, P->Sx16lo, P->Sy16lo, P->lamx_nat,
+                           P->lamy_nat, P->A1T,
+                           P->R12T, P->G, P->n1, P->n2, P->n1p, P->n2p, P->kx, P->ky, P->dpen, s));
+    return RSFDE_OK;
+  }
   if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
   const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
   const double N = (double)P->N, S = (double)(P->n1 + 1) * (double)P->n2;
@@ -318,9 +370,9 @@ int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RSFDE_EINVAL;
   if (o->precond != RSFDE_PRECOND_TAU && o->precond != RSFDE_PRECOND_NONE) return RSFDE_EINVAL;
   if (o->precision < RSFDE_FP64 || o->precision > RSFDE_BF16) return RSFDE_EINVAL;
-  if (o->precond == RSFDE_PRECOND_TAU) {
+  if (o->reorth < -1 || o->reorth > 1) return RSFDE_EINVAL;
+  if (o->precond == RSFDE_PRECOND_TAU && o->precision != RSFDE_BF16) {
     if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
-    if (o->precision == RSFDE_BF16) return RSFDE_EUNSUPPORTED;
   }
   return RSFDE_OK;
 }
@@ -354,6 +406,11 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
     return finish(st, RSFDE_OK, 0, 0, 0.0, 0.0);
   }
   const double thresh = o->tol * bnorm;
+  // Reorthogonalisation: on request, and by default with the BF16
+  // preconditioner, whose rounding makes single-pass Gram-Schmidt lose
+  // orthogonality (the cycle minimum is then no longer the true residual).
+  const bool reorth = o->reorth > 0 || (o->reorth == 0 && o->precond == RSFDE_PRECOND_TAU &&
+                                        o->precision == RSFDE_BF16);
   int total = 0, cycles = 0;
   double beta = 0.0;
   for (;;) {
@@ -384,14 +441,26 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
       }
       rc = matvec_impl(P, zj, P->w, s);
       if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+      double* vnext = P->V + (size_t)(j + 1) * ld;
       {
         ProfScope ps(P, s, kCatMultidot, 8.0 * (j + 2) * (double)N);
-        CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, s));
+        CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, false, s));
       }
       {
         ProfScope ps(P, s, kCatAxpy, 8.0 * (j + 3) * (double)N);
-        CK(launch_axpy_givens(P->V, ld, j + 1, P->w, P->V + (size_t)(j + 1) * ld, N, P->rw,
-                              P->ks, j, P->hs_dev, s));
+        CK(launch_axpy_givens(P->V, ld, j + 1, P->w, vnext, N, P->rw, P->ks, j, false, !reorth,
+                              P->hs_dev, s));
+      }
+      if (reorth) {  // classical Gram-Schmidt, second pass
+        {
+          ProfScope ps(P, s, kCatMultidot, 8.0 * (j + 2) * (double)N);
+          CK(launch_multidot(P->V, ld, j + 1, vnext, N, P->rw, P->ks, j, true, s));
+        }
+        {
+          ProfScope ps(P, s, kCatAxpy, 8.0 * (j + 3) * (double)N);
+          CK(launch_axpy_givens(P->V, ld, j + 1, vnext, vnext, N, P->rw, P->ks, j, true, true,
+                                P->hs_dev, s));
+        }
       }
       CK(hipEventRecord(P->ev[j & 1], s));
       // Look one iteration behind: the device runs step j while the host
@@ -573,6 +642,31 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
         upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess ||
         upload(P, &P->mirror, mirror, s) != hipSuccess)
+      return fail(RSFDE_ENOMEM);
+  }
+  // BF16 / MFMA preconditioner: padded sine matrices, natural-order eigenvalues
+  {
+    P->n1p = (n1 + 127) / 128 * 128;
+    P->n2p = (n2 + 127) / 128 * 128;
+    const std::vector<double> lx = tau_eigs(tx), ly = tau_eigs(ty);
+    std::vector<float> lxn(P->n1p, 0.f), lyn(P->n2p, 0.f);
+    for (int i = 0; i < n1; ++i) lxn[i] = (float)lx[i];
+    for (int j = 0; j < n2; ++j) lyn[j] = (float)ly[j];
+    std::vector<uint16_t> sx, sxl, sy, syl;
+    sine_matrix_bf16(n1, P->n1p, sx, sxl);
+    sine_matrix_bf16(n2, P->n2p, sy, syl);
+    uint16_t *sxd = nullptr, *syd = nullptr, *sxld = nullptr, *syld = nullptr;
+    if (upload(P, &sxd, sx, s) != hipSuccess || upload(P, &syd, sy, s) != hipSuccess ||
+        upload(P, &sxld, sxl, s) != hipSuccess || upload(P, &syld, syl, s) != hipSuccess ||
+        upload(P, &P->lamx_nat, lxn, s) != hipSuccess || upload(P, &P->lamy_nat, lyn, s) != hipSuccess)
+      return fail(RSFDE_ENOMEM);
+    P->Sx16 = (__bf16*)sxd;
+    P->Sy16 = (__bf16*)syd;
+    P->Sx16lo = (__bf16*)sxld;
+    P->Sy16lo = (__bf16*)syld;
+    const size_t pp = (size_t)P->n1p * (size_t)P->n2p;
+    if (P->dalloc(&P->A1T, 2 * pp) != hipSuccess || P->dalloc(&P->R12T, 2 * pp) != hipSuccess ||
+        P->dalloc(&P->G, 2 * pp) != hipSuccess)
       return fail(RSFDE_ENOMEM);
   }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(RSFDE_EHIP);

@@ -181,3 +181,53 @@ def test_long_and_short_restarts(restart):
         u = u.cpu().numpy().reshape(w.n2, w.n1)
     err = np.abs(u - ref).max() / np.abs(ref).max()
     assert err <= 1e-10, (restart, err, iters)
+
+
+BF16_SHAPES = [(1, 1), (7, 3), (20, 33), (63, 63), (100, 130), (255, 255), (300, 129)]
+
+
+@pytest.mark.parametrize("n1,n2", BF16_SHAPES)
+def test_precond_bf16_mfma_close_to_fp64(n1, n2):
+    """BF16-operand / FP32-accumulate sine-matrix GEMMs (any n, including sizes
+    that are not 2^k - 1) against the FP64 oracle.  Each of the four products
+    rounds its operands to BF16 (relative 2^-9), so the apply agrees to ~1e-2:
+    the test bound is 4e-2 of ||z||_inf."""
+    p = _problem(n1, n2, seed=3)
+    rng = np.random.default_rng(17 + n1 * n2)
+    V = rng.standard_normal((n2, n1))
+    ref = O.precond_apply(p, V)
+    with _plan(p) as pl:
+        out = pl.precond(_t(V), precision="bf16").cpu().numpy().reshape(n2, n1)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    assert err <= 4e-2, err
+
+
+@pytest.mark.parametrize("name,n,m", [("c3", 31, 2), ("c1", 20, 2), ("c5", 33, 2)])
+def test_step_bf16_preconditioner_matches_lu(name, n, m):
+    """Flexible GMRES with the BF16 preconditioner reaches the FP64 solution:
+    the outer residual, Arnoldi and update stay FP64."""
+    w = make_config(name, n=n, m=m)
+    p = O.problem_from_workload(w)
+    ref = O.march_lu(p, w.u0, w.m, w.f_kind)
+    with RsfdePlan.from_workload(w) as pl:
+        u, iters, _ = pl.march(_t(w.u0), w.m, w.f_kind,
+                               make_opts(w.restart, 10000, 1e-12, precision="bf16"))
+        u = u.cpu().numpy().reshape(w.n2, w.n1)
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    assert err <= 1e-10, (err, iters)
+
+
+@pytest.mark.parametrize("precision,reorth", [("fp64", 1), ("fp32", 1), ("bf16", -1), ("bf16", 1)])
+def test_reorthogonalisation_option(precision, reorth):
+    """One or two classical Gram-Schmidt passes, any preconditioner precision: the
+    converged solution matches LU."""
+    w = make_config("c3", n=31, m=2)
+    p = O.problem_from_workload(w)
+    ref = O.march_lu(p, w.u0, w.m, w.f_kind)
+    with RsfdePlan.from_workload(w) as pl:
+        u, iters, _ = pl.march(_t(w.u0), w.m, w.f_kind,
+                               make_opts(w.restart, 10000, 1e-12, precision=precision,
+                                         reorth=reorth))
+        u = u.cpu().numpy().reshape(w.n2, w.n1)
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    assert err <= 1e-10, (err, iters)
