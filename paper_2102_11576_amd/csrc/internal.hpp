@@ -11,7 +11,7 @@ namespace rsfde {
 
 constexpr int kMaxRestart = 64;       // largest GMRES restart length supported
 constexpr int kRedThreads = 256;      // threads per block of the streaming reductions
-constexpr int kMaxRedBlocks = 1024;   // upper bound on blocks of a streaming reduction
+constexpr int kMaxRedBlocks = 512;    // upper bound on blocks of a streaming reduction
 constexpr int kMinLog2L = 1;          // FFT lengths 2 .. 16384
 constexpr int kMaxLog2L = 14;
 

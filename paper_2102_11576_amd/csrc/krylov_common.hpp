@@ -66,8 +66,17 @@ __device__ __forceinline__ void publish_partials(double (&acc)[NV], int nv, RedW
 // fixed order (lane-strided, then a butterfly) and returns the total in every lane.
 __device__ __forceinline__ double wave_total(const RedWork& rw, int v, int nb) {
   const int lane = threadIdx.x & 63;
+  const double* p = rw.partial + (size_t)v * kMaxRedBlocks;
+  // all loads first (independent addresses), then the fixed-order sum
+  double x[kMaxRedBlocks / 64];
+#pragma unroll
+  for (int q = 0; q < kMaxRedBlocks / 64; ++q) {
+    const int k = lane + 64 * q;
+    x[q] = k < nb ? p[k] : 0.0;
+  }
   double s = 0.0;
-  for (int k = lane; k < nb; k += 64) s += rw.partial[(size_t)v * kMaxRedBlocks + k];
+#pragma unroll
+  for (int q = 0; q < kMaxRedBlocks / 64; ++q) s += x[q];
   return wave_sum(s);
 }
 
