@@ -60,6 +60,12 @@ extern "C" {
 #define RSFDE_F_LOGISTIC 1 /* f = u (1 - u) */
 #define RSFDE_F_SIN 2      /* f = sin u */
 #define RSFDE_F_CUBIC 3    /* f = u - u^3 */
+#define RSFDE_F_DECAY 4    /* f = -u (with a source field: Example 1 of Section 5) */
+
+/* preconditioning side (rsfde_solver_opts.side) */
+#define RSFDE_RIGHT 0 /* flexible GMRES on M P^{-1}; stop on ||b - M x|| <= tol ||b|| */
+#define RSFDE_LEFT 1  /* GMRES on P^{-1} M; stop on the estimate of ||P^{-1}(b - M x)||
+                         <= tol ||P^{-1} b||: the stopping rule of Section 5 */
 
 typedef struct rsfde_plan_s* rsfde_plan;
 
@@ -72,12 +78,13 @@ typedef struct {
 typedef struct {
   int32_t restart;   /* GMRES restart length, 1 .. max_restart of the plan */
   int32_t max_iters; /* cap on inner iterations per solve (>= 1) */
-  double tol;        /* stop when ||b - M x||_2 <= tol * ||b||_2 (tol > 0) */
+  double tol;        /* relative tolerance > 0 of the stopping rule of `side` */
   int32_t precision; /* RSFDE_FP64 / RSFDE_FP32 / RSFDE_BF16: preconditioner arithmetic */
   int32_t precond;   /* RSFDE_PRECOND_TAU or RSFDE_PRECOND_NONE */
   int32_t reorth;    /* Gram-Schmidt passes: 1 = two (CGS2), -1 = one (CGS),
                         0 = default: two with the BF16 preconditioner, else one */
-  int32_t reserved;
+  int32_t side;      /* RSFDE_RIGHT (default) or RSFDE_LEFT; with RSFDE_PRECOND_NONE
+                        both are plain GMRES */
 } rsfde_solver_opts;
 
 typedef struct {
@@ -85,8 +92,9 @@ typedef struct {
   int32_t restarts;   /* restart cycles started */
   int32_t status;     /* same code as the return value */
   int32_t reserved;
-  double relres;      /* true relative residual ||b - M x|| / ||b|| at exit */
-  double bnorm;       /* ||b||_2 */
+  double relres;      /* relative residual at exit: true ||b - M x|| / ||b|| (right), or
+                         the estimate of ||P^{-1}(b - M x)|| / ||P^{-1} b|| (left) */
+  double bnorm;       /* ||b||_2 (right) or ||P^{-1} b||_2 (left) */
 } rsfde_stats;
 
 /*
@@ -103,11 +111,12 @@ typedef struct {
  *   eta, dt     : penalty parameter > 0 and time step > 0
  *   max_restart : largest restart the plan will run (1..64; <= 0 means 30)
  *   stream      : stream for the set-up uploads
- * The FP64 / FP32 sine-transform preconditioner requires n1+1 and n2+1 to be
- * powers of two (FFT lengths 2(n+1)); other sizes support the matrix-vector
- * product, RSFDE_PRECOND_NONE and the BF16 preconditioner.  Sizes up to
- * n = 8191 per direction.
- * Errors: EINVAL, ENOMEM, EHIP.
+ * Any n1, n2 from 1 to 4096 (EUNSUPPORTED above).  When n1+1 and n2+1 are
+ * powers of two the FP64 / FP32 preconditioner runs its sine transforms as
+ * FFTs of the odd extension (length 2(n+1)); otherwise as chirp convolutions
+ * (Bluestein) on power-of-two FFTs of length >= 2n-1, about four times the
+ * arithmetic for the same result.
+ * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED.
  */
 int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double alpha2,
                 double kx, double ky, const uint8_t* mask_dev, double eta, double dt,
@@ -125,22 +134,35 @@ int rsfde_matvec(rsfde_plan plan, const double* x, double* y, void* stream);
 /* z = P_hat^{-1} r (preconditioner): 2-D DST-I, the two eigenvalue scalings
  * 1/(1 - lx_i - ly_j) and 1/(1 + dt/eta - lx_i - ly_j), inverse 2-D DST-I,
  * combined by the mask.  precision selects the internal arithmetic: FP64 or
- * FP32 run the transforms as FFTs (n1+1, n2+1 powers of two); BF16 runs them
- * as dense sine-matrix products on the matrix cores (BF16 operands, FP32
- * accumulation; any n).  r and z must not overlap.
- * Errors: EINVAL, EUNSUPPORTED, EHIP. */
+ * FP32 run the transforms as FFTs (odd extension when n+1 is a power of two,
+ * chirp convolution otherwise); BF16 runs them as dense sine-matrix products
+ * on the matrix cores (BF16 operands, FP32 accumulation).  Any n.  r and z
+ * must not overlap.
+ * Errors: EINVAL, EHIP. */
 int rsfde_precond_apply(rsfde_plan plan, const double* r, double* z, int32_t precision,
                         void* stream);
 
 /* One implicit time step (difference_scheme / linearsystem):
  *   b = u_prev + dt * mask * f(u_prev),  solve M u_next = b
- * by restarted right-preconditioned flexible GMRES, initial guess
- * 2 u_prev - u_prev2 (u_prev if u_prev2 is NULL) as in Section 5.
+ * by restarted GMRES (opts->side: right-preconditioned flexible GMRES, or the
+ * left-preconditioned form of Section 5), initial guess 2 u_prev - u_prev2
+ * (u_prev if u_prev2 is NULL) as in Section 5.
  * u_next may alias u_prev2 (but not u_prev).  stats may be NULL.
  * Errors: EINVAL, ENOTCONV (u_next holds the last iterate), ENONFINITE, EHIP. */
 int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
                const rsfde_solver_opts* opts, double* u_next, rsfde_stats* stats,
                void* stream);
+
+/* rsfde_step with an x,y,t-dependent source field (Section 2 allows f to depend
+ * on x, y and t; Example 1 of Section 5 is f = -u + g(x, y, t)):
+ *   b = u_prev + dt * mask * (f(u_prev) + src_scale * src)
+ * src: device array [n2][n1] (NULL: no field term, as rsfde_step), read only;
+ * src_scale: finite scalar (e.g. a time factor, so one stored field serves
+ * every step of a separable source).  src must not alias u_next.
+ * Errors: as rsfde_step. */
+int rsfde_step_src(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
+                   const double* src, double src_scale, const rsfde_solver_opts* opts,
+                   double* u_next, rsfde_stats* stats, void* stream);
 
 /* Solve M x = b for a caller-supplied right-hand side (used by the adjoint
  * and by tests).  x holds the initial guess on entry and the solution on exit.

@@ -40,7 +40,7 @@ import numpy as np
 import scipy.linalg as sla
 
 # Source-term kinds (same integer codes as the input generator / C ABI).
-F_NONE, F_LOGISTIC, F_SIN, F_CUBIC = 0, 1, 2, 3
+F_NONE, F_LOGISTIC, F_SIN, F_CUBIC, F_DECAY = 0, 1, 2, 3, 4
 
 __all__ = [
     "gl_weights", "riesz_c", "mesh_widths", "toeplitz_first_column", "G_dense",
@@ -50,8 +50,8 @@ __all__ = [
     "tau_eigs_dense", "tau_eigs_xy", "precond_dense", "precond_apply", "P_dense",
     "gmres", "march_gmres", "adjoint_lu", "loss_and_grads_lu",
     "matvec_fast", "precond_apply_fft", "matvec_entry",
-    "example1_exact", "example1_source", "example1_march",
-    "F_NONE", "F_LOGISTIC", "F_SIN", "F_CUBIC",
+    "example1_march",
+    "F_NONE", "F_LOGISTIC", "F_SIN", "F_CUBIC", "F_DECAY",
 ]
 
 
@@ -199,6 +199,8 @@ def f_eval(kind: int, u: np.ndarray) -> np.ndarray:
         return np.sin(u)
     if kind == F_CUBIC:
         return u - u ** 3
+    if kind == F_DECAY:
+        return -u
     raise ValueError(kind)
 
 
@@ -211,6 +213,8 @@ def fprime_eval(kind: int, u: np.ndarray) -> np.ndarray:
         return np.cos(u)
     if kind == F_CUBIC:
         return 1.0 - 3.0 * u * u
+    if kind == F_DECAY:
+        return -np.ones_like(u)
     raise ValueError(kind)
 
 
@@ -525,56 +529,16 @@ def loss_and_grads_lu(w, u_tgt: np.ndarray, kx: float, ky: float, u0=None):
 # Section 5, Example 1: manufactured solution on the ellipse.
 # ---------------------------------------------------------------------------
 
-def example1_exact(X, Y, t, a=2.0, b=1.0):
-    """u = e^{-t} ((x-a)^2/a^2 + (y-b)^2/b^2 - 1)^2 inside the ellipse, 0 outside."""
-    q = (X - a) ** 2 / a ** 2 + (Y - b) ** 2 / b ** 2
-    return np.where(q <= 1.0, math.exp(-t) * (q - 1.0) ** 2, 0.0)
-
-
-def _h_term(alpha, s, d):
-    """Riemann-Liouville derivative of order alpha of s^2 (2d - s)^2 / const:
-    24 s^{4-a}/G(5-a) - 24 d s^{3-a}/G(4-a) + 8 d^2 s^{2-a}/G(3-a)."""
-    s = np.maximum(s, 0.0)
-    return (24.0 * s ** (4.0 - alpha) / math.gamma(5.0 - alpha)
-            - 24.0 * d * s ** (3.0 - alpha) / math.gamma(4.0 - alpha)
-            + 8.0 * d * d * s ** (2.0 - alpha) / math.gamma(3.0 - alpha))
-
-
-def example1_source(u, X, Y, t, alpha1, alpha2, kx, ky, a=2.0, b=1.0):
-    """Source f(u, x, y, t) of Example 1, re-derived from the exact solution.
-
-    On the chord through (x, y) the exact solution is
-    e^{-t} a^{-4} s^2 (2c - s)^2 with s the distance to the left boundary and c the
-    half chord, so the left and right RL derivatives are e^{-t} a^{-4} h(alpha, s, c)
-    with h as in _h_term (power rule D^a s^p = G(p+1)/G(p+1-a) s^{p-a}).  Then
-    f = u_t - kx R_x u - ky R_y u with u_t = -u.  The printed formula of the
-    example has a^4 for a^{-4}, + for - in front of the fractional terms and
-    s^{3-alpha} for s^{2-alpha} in the last term of h; this is the corrected
-    reading (listed in the design doc).  Zero outside the domain (zero extension).
-    """
-    q = (X - a) ** 2 / a ** 2 + (Y - b) ** 2 / b ** 2
-    inside = q <= 1.0
-    cyh = a * np.sqrt(np.maximum(1.0 - (Y - b) ** 2 / b ** 2, 0.0))  # half chord along x
-    cxh = b * np.sqrt(np.maximum(1.0 - (X - a) ** 2 / a ** 2, 0.0))  # half chord along y
-    e = math.exp(-t)
-    Rx = riesz_c(alpha1) * e * a ** -4 * (_h_term(alpha1, X - a + cyh, cyh) + _h_term(alpha1, a + cyh - X, cyh))
-    Ry = riesz_c(alpha2) * e * b ** -4 * (_h_term(alpha2, Y - b + cxh, cxh) + _h_term(alpha2, b + cxh - Y, cxh))
-    f = -u - kx * Rx - ky * Ry
-    return np.where(inside, f, 0.0)
-
-
 def example1_march(w, side: str = "left", precond: bool = True, tol: Optional[float] = None,
                    use_lu: bool = False):
     """Run Example 1 as in Section 5 (T, m, eta, GMRES(20), tol 1e-8 by default).
 
+    The source f(u, x, y, t) = -u + e^{-t} g0 is taken at t_{k-1} (f_approximation);
+    g0 and the exact solution come with the workload (input fields).
     Returns (error, mean iterations per step, u^m, penalty-region max |u|)."""
-    from workloads.configs import interior_coords  # input coordinates only
     p = problem_from_workload(w)
-    a, b = w.extra["a"], w.extra["b"]
-    x, y = interior_coords(w.n1, w.n2, w.box)
-    X, Y = np.meshgrid(x, y)
-    fn = lambda km1, u: example1_source(u, X, Y, km1 * p.dt, w.alpha1, w.alpha2,  # noqa: E731
-                                        w.kx, w.ky, a, b)
+    g0 = w.extra["src"]
+    fn = lambda km1, u: f_eval(F_DECAY, u) + math.exp(-km1 * p.dt) * g0  # noqa: E731
     if use_lu:
         lu = sla.lu_factor(dense_M(p))
         u = w.u0.copy()
@@ -585,7 +549,7 @@ def example1_march(w, side: str = "left", precond: bool = True, tol: Optional[fl
     else:
         u, iters = march_gmres(p, w.u0, w.m, F_NONE, w.restart, w.tol if tol is None else tol,
                                side=side, precond=precond, f_values_fn=fn)
-    ue = example1_exact(X, Y, w.T, a, b)
+    ue = math.exp(-w.T) * w.extra["exact0"]
     inside = w.mask.astype(bool)
     err = np.max(np.abs(ue - u)[inside]) / np.max(np.abs(ue)[inside])
     pen = np.max(np.abs(u[~inside])) if (~inside).any() else 0.0

@@ -25,7 +25,8 @@ RSFDE_EUNSUPPORTED = -7
 
 RSFDE_FP64, RSFDE_FP32, RSFDE_BF16 = 0, 1, 2
 RSFDE_PRECOND_TAU, RSFDE_PRECOND_NONE = 0, 1
-RSFDE_F_NONE, RSFDE_F_LOGISTIC, RSFDE_F_SIN, RSFDE_F_CUBIC = 0, 1, 2, 3
+RSFDE_F_NONE, RSFDE_F_LOGISTIC, RSFDE_F_SIN, RSFDE_F_CUBIC, RSFDE_F_DECAY = 0, 1, 2, 3, 4
+RSFDE_RIGHT, RSFDE_LEFT = 0, 1
 
 PRECISIONS = {"fp64": RSFDE_FP64, "fp32": RSFDE_FP32, "bf16": RSFDE_BF16}
 
@@ -39,7 +40,7 @@ class rsfde_grid(C.Structure):
 class rsfde_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("reorth", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("side", C.c_int32)]
 
 
 class rsfde_stats(C.Structure):
@@ -71,6 +72,8 @@ def _load():
     lib.rsfde_precond_apply.argtypes = [P, P, P, C.c_int32, P]
     lib.rsfde_step.argtypes = [P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P,
                                C.POINTER(rsfde_stats), P]
+    lib.rsfde_step_src.argtypes = [P, P, P, C.c_int32, P, C.c_double,
+                                   C.POINTER(rsfde_solver_opts), P, C.POINTER(rsfde_stats), P]
     lib.rsfde_solve.argtypes = [P, P, P, C.POINTER(rsfde_solver_opts), C.POINTER(rsfde_stats), P]
     lib.rsfde_adjoint_step.argtypes = [P, P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P, P,
                                        P, C.POINTER(rsfde_stats), P]
@@ -81,7 +84,7 @@ def _load():
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
     for f in ("rsfde_setup", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
-              "rsfde_step", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy",
+              "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy",
               "rsfde_profile", "rsfde_profile_read"):
         getattr(lib, f).restype = C.c_int
     return lib
@@ -128,12 +131,16 @@ def _raise(rc, where):
         raise RsfdeError(rc, where)
 
 
-def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0):
-    """reorth: 1 = two Gram-Schmidt passes, -1 = one, 0 = two only with BF16."""
+def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0,
+              side="right"):
+    """reorth: 1 = two Gram-Schmidt passes, -1 = one, 0 = two only with BF16.
+    side: "right" (flexible GMRES, true-residual stop) or "left" (the stopping
+    rule of the paper's experiments)."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
         if isinstance(precond, str) else int(precond)
-    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), 0)
+    sd = {"right": RSFDE_RIGHT, "left": RSFDE_LEFT}[side] if isinstance(side, str) else int(side)
+    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), sd)
 
 
 def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30, stream=None):
@@ -168,6 +175,17 @@ def rsfde_step(plan, u_prev, u_prev2, f_kind, opts, u_next, stream=None, check=T
                          _ptr(u_next), C.byref(st), _stream(stream))
     if check:
         _raise(rc, "rsfde_step")
+    return st
+
+
+def rsfde_step_src(plan, u_prev, u_prev2, f_kind, src, src_scale, opts, u_next, stream=None,
+                   check=True):
+    st = rsfde_stats()
+    rc = _lib.rsfde_step_src(plan, _ptr(u_prev), _ptr(u_prev2), int(f_kind), _ptr(src),
+                             float(src_scale), C.byref(opts), _ptr(u_next), C.byref(st),
+                             _stream(stream))
+    if check:
+        _raise(rc, "rsfde_step_src")
     return st
 
 

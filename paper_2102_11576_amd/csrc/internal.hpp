@@ -12,14 +12,12 @@ namespace rsfde {
 constexpr int kMaxRestart = 64;       // largest GMRES restart length supported
 constexpr int kRedThreads = 256;      // threads per block of the streaming reductions
 constexpr int kMaxRedBlocks = 512;    // upper bound on blocks of a streaming reduction
-constexpr int kMinLog2L = 1;          // FFT lengths 2 .. 16384
-constexpr int kMaxLog2L = 14;
+constexpr int kMaxN = 4096;           // grid points per direction (FFT lengths <= 8192)
 
 // Points per thread of the register-resident FFT of length L.
 constexpr int fft_pts(int L) { return L < 16 ? L : (L >= 8192 ? 8 : 16); }
-// Pass B of the preconditioner keeps half a spectrum in registers besides the
-// FFT data, so it runs radix-8.
-constexpr int pc_cols_pts(int L) { return L < 16 ? L : (L >= 16384 ? 8 : 16); }
+// Points per thread in pass B of the power-of-two preconditioner.
+constexpr int pc_cols_pts(int L) { return L < 16 ? L : 16; }
 
 // Values the device writes for the host after each Arnoldi step.  Lives in
 // pinned, device-visible host memory; the host reads it after an event.
@@ -79,6 +77,22 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
                               const uint8_t* mask, double* z, const void* tw,
                               int n1, int n2, hipStream_t s);
 
+// Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
+// power of two): T internals, tables chn (n entries) and khat (L entries, in
+// register-position order) per direction; W1 holds n1*n2 T values, Y1 and Y2
+// likewise.  L >= 2n - 1 is the convolution length of that direction.
+template <typename T>
+hipError_t launch_cd_rows_fwd(int L, const double* v, const double* sig, T* W1, const void* chn,
+                              const void* khat, const void* tw, int n1, int n2, hipStream_t s);
+template <typename T>
+hipError_t launch_cd_cols(int L, const T* W1, T* Y1, T* Y2, const double* lamx,
+                          const double* lamy, const void* chn, const void* khat, const void* tw,
+                          int n1, int n2, double kx, double ky, double dpen, hipStream_t s);
+template <typename T>
+hipError_t launch_cd_rows_inv(int L, const T* Y1, const T* Y2, const uint8_t* mask, double* z,
+                              const void* chn, const void* khat, const void* tw, int n1, int n2,
+                              hipStream_t s);
+
 // BF16 / MFMA form of the same preconditioner (dense sine-transform GEMMs,
 // any n; dimensions padded to multiples of 128).  A1T holds 2 n1p n2p values
 // (hi and lo parts of the split intermediate).
@@ -90,9 +104,13 @@ hipError_t launch_pc_gemm_bf16(const double* v, const double* sig, double* z, co
                                double dpen, hipStream_t s);
 
 // ---------------------------- Krylov kernels ------------------------------
+// b = u + dt * mask * (f(u) + src_scale * src)  (src may be NULL), x0 = 2u - u2
+// (or u), ||b|| -> hs->bnorm.
 hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
-                      int f_kind, double* b, double* x0, size_t N, RedWork rw,
-                      HostStatus* hs, hipStream_t s);
+                      int f_kind, const double* src, double src_scale, double* b, double* x0,
+                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s);
+// ||v|| -> hs->bnorm.
+hipError_t launch_norm(const double* v, size_t N, RedWork rw, HostStatus* hs, hipStream_t s);
 hipError_t launch_residual(const double* b, const double* w, double* r, size_t N,
                            RedWork rw, KrylovState* ks, HostStatus* hs, hipStream_t s);
 // h_i = <v_i, w>, i < nv, into column j of H (second = false) or into ks->h2
@@ -105,8 +123,10 @@ hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w,
 hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w,
                               double* vout, size_t N, RedWork rw, KrylovState* ks, int j,
                               bool second, bool finish, HostStatus* hs, hipStream_t s);
+// x += sum_{i<jc} y_i Z_i with R y = g; scaled = true multiplies y_i by
+// vscale[i] (Z = the unnormalised basis V: left preconditioning).
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                         KrylovState* ks, hipStream_t s);
+                         KrylovState* ks, bool scaled, hipStream_t s);
 hipError_t launch_scale_copy(const double* v, const double* sig, double* z, size_t N,
                              hipStream_t s);
 hipError_t launch_adj_lambda(const double* mu, const double* u_prev, const uint8_t* mask,

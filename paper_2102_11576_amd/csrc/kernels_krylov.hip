@@ -3,9 +3,9 @@
 // implicit time step (right-hand side of the linear system of Section 2).
 //
 // Reductions are deterministic: every block reduces its share in a fixed order
-// and publishes one partial per value; the last block to finish (ticket
-// counter) adds the partials in block order and finishes the step (Hessenberg
-// entries, Givens rotation, residual estimate).  The Krylov basis is stored
+// and publishes one partial per value; a one-block finishing kernel launched
+// next adds the partials in block order and finishes the step (norms,
+// Hessenberg entries, Givens rotation, residual estimate).  The Krylov basis is stored
 // unnormalised, v_i = vscale[i] * V_i, which removes a separate normalisation
 // pass: readers apply vscale[i] on the fly.
 #include "krylov_common.hpp"
@@ -24,6 +24,7 @@ __device__ __forceinline__ double f_eval(int kind, double u) {
     case 1: return u * (1.0 - u);
     case 2: return sin(u);
     case 3: return u - u * u * u;
+    case 4: return -u;
     default: return 0.0;
   }
 }
@@ -32,26 +33,30 @@ __device__ __forceinline__ double fprime_eval(int kind, double u) {
     case 1: return 1.0 - 2.0 * u;
     case 2: return cos(u);
     case 3: return 1.0 - 3.0 * u * u;
+    case 4: return -1.0;
     default: return 0.0;
   }
 }
 
 // ------------------------------- kernels ----------------------------------
 
-// b = u + dt * mask * f(u)  (zero extension of f outside the domain);
-// x0 = 2u - u2 (u2 given) or u (first step); partials of ||b||^2 and of the
-// count of non-finite values.
+// b = u + dt * mask * (f(u) + src_scale * src)  (zero extension of the source
+// outside the domain; src = NULL means no field term); x0 = 2u - u2 (u2 given)
+// or u (first step); partials of ||b||^2 and of the count of non-finite values.
 __global__ __launch_bounds__(kRedThreads) void k_rhs(const double* __restrict__ u,
                                                      const double* __restrict__ u2,
                                                      const uint8_t* __restrict__ mask, double dt,
-                                                     int f_kind, double* __restrict__ b,
+                                                     int f_kind, const double* __restrict__ src,
+                                                     double src_scale, double* __restrict__ b,
                                                      double* x0, size_t N, RedWork rw) {
   __shared__ double sh[16 * 2];
   double acc[2] = {0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (size_t)gridDim.x * blockDim.x) {
     const double ui = u[i];
-    const double bi = ui + dt * (double)mask[i] * f_eval(f_kind, ui);
+    double fi = f_eval(f_kind, ui);
+    if (src) fi += src_scale * src[i];
+    const double bi = ui + dt * (double)mask[i] * fi;
     const double xi = u2 ? 2.0 * ui - u2[i] : ui;
     b[i] = bi;
     x0[i] = xi;
@@ -136,6 +141,17 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const double* __restrict__ 
   publish_partials<1>(acc, 1, rw, sh);
 }
 
+// hs->bnorm = sqrt(<a, a>) from k_dot partials
+__global__ __launch_bounds__(kFinishThreads) void k_norm_finish(RedWork rw, int nb, HostStatus* hs) {
+  if ((threadIdx.x >> 6) > 0) return;
+  const double d = wave_total(rw, 0, nb);
+  if (threadIdx.x == 0) {
+    hs->bnorm = sqrt(d);
+    if (!isfinite(d)) hs->flags |= kFlagNonFinite;
+    __threadfence_system();
+  }
+}
+
 // *acc_out += <a, b>
 __global__ __launch_bounds__(kFinishThreads) void k_dot_finish(RedWork rw, int nb, double* acc_out) {
   if ((threadIdx.x >> 6) > 0) return;
@@ -146,11 +162,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_dot_finish(RedWork rw, int n
 // ------------------------------- launchers --------------------------------
 
 hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
-                      int f_kind, double* b, double* x0, size_t N, RedWork rw, HostStatus* hs,
-                      hipStream_t s) {
+                      int f_kind, const double* src, double src_scale, double* b, double* x0,
+                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s) {
   const int nb = red_blocks(N);
-  hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(kRedThreads), 0, s, u, u2, mask, dt, f_kind, b, x0, N,
-                     rw);
+  hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(kRedThreads), 0, s, u, u2, mask, dt, f_kind, src,
+                     src_scale, b, x0, N, rw);
   hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, hs);
   return hipGetLastError();
 }
@@ -173,6 +189,13 @@ hipError_t launch_adj_lambda(const double* mu, const double* u_prev, const uint8
                              double dt, int f_kind, double* lam_prev, size_t N, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_lambda, dim3(red_blocks(N)), dim3(kRedThreads), 0, s, mu, u_prev, mask,
                      dt, f_kind, lam_prev, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const double* v, size_t N, RedWork rw, HostStatus* hs, hipStream_t s) {
+  const int nb = red_blocks(N);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kRedThreads), 0, s, v, v, N, rw);
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, hs);
   return hipGetLastError();
 }
 

@@ -153,7 +153,7 @@ static hipError_t mv_cols_impl(const double* z, const double* t, double* out, co
 }
 
 #define RSFDE_L_CASES(X) \
-  X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+  X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,

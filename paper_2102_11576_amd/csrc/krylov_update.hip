@@ -1,6 +1,9 @@
-// Solution update at the end of a restart cycle of the flexible GMRES:
+// Solution update at the end of a restart cycle:
 // x += sum_{i<jc} y_i Z_i with R y = g (R = the rotated, upper-triangular
-// Hessenberg matrix).  Every block solves the small triangular system itself.
+// Hessenberg matrix).  Z is the preconditioned basis of the flexible GMRES, or
+// (scaled = true) the unnormalised Arnoldi basis V of left preconditioning,
+// whose vectors carry the factors vscale[i].  Every block solves the small
+// triangular system itself.
 #include "krylov_common.hpp"
 
 namespace rsfde {
@@ -9,7 +12,7 @@ template <int NV>
 __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict__ Z, size_t ldz,
                                                         double* __restrict__ x, size_t N,
                                                         const KrylovState* __restrict__ ks,
-                                                        int v0, int jc) {
+                                                        int v0, int jc, bool scaled) {
   __shared__ double y[kMaxRestart];
   if (threadIdx.x == 0) {
     for (int i = jc - 1; i >= 0; --i) {
@@ -22,7 +25,7 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
   __syncthreads();
   double c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v];
+  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v] * (scaled ? ks->vscale[v0 + v] : 1.0);
   const size_t N2 = N / 2;
   double2* x2 = reinterpret_cast<double2*>(x);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2;
@@ -47,11 +50,11 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
 }
 
 using UpdateFn = void (*)(const double*, size_t, double*, size_t, const KrylovState*, int, int,
-                          dim3, hipStream_t);
+                          bool, dim3, hipStream_t);
 template <int NV>
 static void run_update(const double* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
-                       int v0, int jc, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc);
+                       int v0, int jc, bool scaled, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc, scaled);
 }
 template <int... I>
 static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
@@ -60,12 +63,12 @@ static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_se
 static const auto kUpdate = update_table(std::make_integer_sequence<int, kChunk>{});
 
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                         KrylovState* ks, hipStream_t s) {
+                         KrylovState* ks, bool scaled, hipStream_t s) {
   if (jc <= 0) return hipSuccess;
   if (jc > kMaxRestart) return hipErrorInvalidValue;
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, dim3(red_blocks(N)), s);
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, dim3(red_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -256,7 +256,7 @@ static hipError_t pc_rows_inv_impl(const T* P1, const T* P2, const int* mirror,
 }
 
 #define RSFDE_LD_CASES(X) \
-  X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+  X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, const void* tw,

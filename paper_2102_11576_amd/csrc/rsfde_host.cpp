@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
@@ -72,6 +73,7 @@ struct Plan {
   size_t N = 0, ldv = 0;
   double alpha1 = 0, alpha2 = 0, kx = 0, ky = 0, eta = 0, dt = 0, dpen = 0;
   int Lcx = 0, Lcy = 0, Ldx = 0, Ldy = 0;
+  int Lgx = 0, Lgy = 0;  // chirp-DST convolution lengths (0: power-of-two path)
   int max_restart = 0;
 
   uint8_t* mask = nullptr;
@@ -81,6 +83,7 @@ struct Plan {
   double* w = nullptr;
   double* t = nullptr;
   double* mu = nullptr;
+  double* pb = nullptr;  // P_hat^{-1} b (left preconditioning)
   void* Q = nullptr;
   void* P1 = nullptr;
   void* P2 = nullptr;
@@ -91,6 +94,13 @@ struct Plan {
   float* lamx32 = nullptr;
   float* lamy32 = nullptr;
   int* mirror = nullptr;
+  // chirp-form preconditioner (n + 1 not a power of two)
+  double* lamx_n = nullptr;  // tau eigenvalues, natural order, unit k
+  double* lamy_n = nullptr;
+  void* chx[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 tables
+  void* khx[2] = {nullptr, nullptr};
+  void* chy[2] = {nullptr, nullptr};
+  void* khy[2] = {nullptr, nullptr};
   std::map<int, void*> tw64, tw32;
   // BF16 / MFMA preconditioner
   int n1p = 0, n2p = 0;
@@ -159,11 +169,13 @@ hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
 
 enum ProfCat {
   kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
-  kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kNumCats
+  kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kCatCdRows, kCatCdCols,
+  kCatCdRowsInv, kNumCats
 };
 const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
                                          "pc_rows_inv", "multidot", "axpy_givens", "update",
-                                         "residual", "rhs", "other", "pc_gemm_bf16"};
+                                         "residual", "rhs", "other", "pc_gemm_bf16",
+                                         "cd_rows_fwd", "cd_cols", "cd_rows_inv"};
 
 // Brackets one kernel launch with timing events when profiling is on.
 struct ProfScope {
@@ -244,6 +256,63 @@ std::vector<T> twiddles(int L) {
   return tw;
 }
 
+// In-place forward DFT X_f = sum_p a_p exp(-2 pi i p f / L), L a power of two
+// (iterative radix-2 with the symmetric twiddle table).
+void fft_host(std::vector<std::complex<double>>& a) {
+  const int L = (int)a.size();
+  for (int i = 1, j = 0; i < L; ++i) {
+    int bit = L >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  const std::vector<double> tw = twiddles<double>(L);
+  for (int len = 2; len <= L; len <<= 1) {
+    const int step = L / len;
+    for (int i = 0; i < L; i += len)
+      for (int k = 0; k < len / 2; ++k) {
+        const std::complex<double> w(tw[2 * (size_t)(k * step)], tw[2 * (size_t)(k * step) + 1]);
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
+// Tables of the chirp form of the length-n orthonormal DST-I (M = n + 1):
+//   chn[p]  = exp(i pi (p+1)^2 / (2M)), p < n (interleaved re, im);
+//   khat[p] = sqrt(2/M) / L * K_f at f = freq(p), K = DFT_L of the even kernel
+//             k[m mod L] = exp(-i pi m^2 / (2M)), |m| < n.
+// Phases are reduced exactly: m^2 mod 4M in integers.
+void chirp_tables(int n, int L, std::vector<double>& chn, std::vector<double>& khat) {
+  const long long M4 = 4LL * (n + 1);
+  auto ang = [&](long long j) {
+    return kPi * (double)((j * j) % M4) / (2.0 * (double)(n + 1));
+  };
+  chn.assign(2 * (size_t)n, 0.0);
+  for (int p = 0; p < n; ++p) {
+    const double a = ang(p + 1);
+    chn[2 * (size_t)p] = std::cos(a);
+    chn[2 * (size_t)p + 1] = std::sin(a);
+  }
+  std::vector<std::complex<double>> k(L, {0.0, 0.0});
+  for (int m = 0; m < n; ++m) {
+    const double a = ang(m);
+    const std::complex<double> c(std::cos(a), -std::sin(a));
+    k[m] = c;
+    if (m) k[L - m] = c;
+  }
+  fft_host(k);
+  const double sc = std::sqrt(2.0 / (n + 1)) / (double)L;
+  const int P = fft_pts(L);
+  khat.assign(2 * (size_t)L, 0.0);
+  for (int p = 0; p < L; ++p) {
+    const std::complex<double> v = k[fft_freq(L, P, p)] * sc;
+    khat[2 * (size_t)p] = v.real();
+    khat[2 * (size_t)p + 1] = v.imag();
+  }
+}
+
 // float -> bf16, round to nearest even (finite inputs).
 uint16_t to_bf16_bits(float f) {
   uint32_t u;
@@ -312,6 +381,30 @@ int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s) {
   return RSFDE_OK;
 }
 
+// Chirp-form P_hat^{-1} (any n): three passes with T internals.
+template <typename T>
+int precond_chirp(Plan* P, const double* r, const double* sig, double* z, int t,
+                  std::map<int, void*>& tw, hipStream_t s) {
+  const double N = (double)P->N, ts = (double)sizeof(T);
+  T *W = (T*)P->Q, *Y1 = (T*)P->P1, *Y2 = (T*)P->P2;
+  {
+    ProfScope ps(P, s, kCatCdRows, 8.0 * N + ts * N);
+    CK(launch_cd_rows_fwd<T>(P->Lgx, r, sig, W, P->chx[t], P->khx[t], tw[P->Lgx], P->n1, P->n2,
+                             s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdCols, 3.0 * ts * N);
+    CK(launch_cd_cols<T>(P->Lgy, W, Y1, Y2, P->lamx_n, P->lamy_n, P->chy[t], P->khy[t],
+                         tw[P->Lgy], P->n1, P->n2, P->kx, P->ky, P->dpen, s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdRowsInv, 2.0 * ts * N + 9.0 * N);
+    CK(launch_cd_rows_inv<T>(P->Lgx, Y1, Y2, P->mask, z, P->chx[t], P->khx[t], tw[P->Lgx], P->n1,
+                             P->n2, s));
+  }
+  return RSFDE_OK;
+}
+
 int precond_impl(Plan* P, const double* r, const double* sig, double* z, int precision,
                  hipStream_t s) {
   if (precision == RSFDE_BF16) {
@@ -321,7 +414,11 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
                            P->R12T, P->G, P->n1, P->n2, P->n1p, P->n2p, P->kx, P->ky, P->dpen, s));
     return RSFDE_OK;
   }
-  if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
+  if (P->Lgx) {
+    if (precision == RSFDE_FP64) return precond_chirp<double>(P, r, sig, z, 0, P->tw64, s);
+    if (precision == RSFDE_FP32) return precond_chirp<float>(P, r, sig, z, 1, P->tw32, s);
+    return RSFDE_EUNSUPPORTED;
+  }
   const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
   const double N = (double)P->N, S = (double)(P->n1 + 1) * (double)P->n2;
   if (precision == RSFDE_FP64) {
@@ -371,9 +468,8 @@ int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (o->precond != RSFDE_PRECOND_TAU && o->precond != RSFDE_PRECOND_NONE) return RSFDE_EINVAL;
   if (o->precision < RSFDE_FP64 || o->precision > RSFDE_BF16) return RSFDE_EINVAL;
   if (o->reorth < -1 || o->reorth > 1) return RSFDE_EINVAL;
-  if (o->precond == RSFDE_PRECOND_TAU && o->precision != RSFDE_BF16) {
-    if (P->Ldx == 0 || P->Ldy == 0) return RSFDE_EUNSUPPORTED;
-  }
+  if (o->side != RSFDE_RIGHT && o->side != RSFDE_LEFT) return RSFDE_EINVAL;
+  (void)P;
   return RSFDE_OK;
 }
 
@@ -392,31 +488,52 @@ int finish(rsfde_stats* st, int code, int iters, int restarts, double beta, doub
   return code;
 }
 
-// Restarted right-preconditioned flexible GMRES on M x = P->b (bnorm already
-// in hs->bnorm).  x holds the initial guess and receives the solution.
+// Restarted GMRES on M x = P->b (||b|| already in hs->bnorm); x holds the
+// initial guess and receives the solution.
+//  right (default): flexible GMRES, z_j = P_hat^{-1} v_j stored per step,
+//    x += Z y; every cycle restarts from the true residual b - M x and the
+//    solve stops when ||b - M x|| <= tol ||b||.
+//  left (the convention of the experiments of Section 5): Arnoldi on
+//    P_hat^{-1} M, x += V y; stops when the residual estimate of
+//    ||P_hat^{-1}(b - M x)|| is <= tol ||P_hat^{-1} b||.
 int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s) {
   const size_t N = P->N, ld = P->ldv;
   volatile HostStatus* hs = P->hs;
+  const bool tau = o->precond == RSFDE_PRECOND_TAU;
+  const bool left = tau && o->side == RSFDE_LEFT;
+  int rc = RSFDE_OK;
   CK(hipStreamSynchronize(s));
   if (vread(&hs->flags) & kFlagNonFinite) return finish(st, RSFDE_ENONFINITE, 0, 0, 0, 0);
-  const double bnorm = vread(&hs->bnorm);
+  double bnorm = vread(&hs->bnorm);
   if (bnorm == 0.0) {
     CK(hipMemsetAsync(x, 0, N * sizeof(double), s));
     CK(hipStreamSynchronize(s));
     return finish(st, RSFDE_OK, 0, 0, 0.0, 0.0);
   }
+  if (left) {  // reference norm ||P_hat^{-1} b||
+    rc = precond_impl(P, P->b, nullptr, P->pb, o->precision, s);
+    if (rc) return finish(st, rc, 0, 0, 0, bnorm);
+    CK(launch_norm(P->pb, N, P->rw, P->hs_dev, s));
+    CK(hipStreamSynchronize(s));
+    if (vread(&hs->flags) & kFlagNonFinite) return finish(st, RSFDE_ENONFINITE, 0, 0, 0, 0);
+    bnorm = vread(&hs->bnorm);
+  }
   const double thresh = o->tol * bnorm;
   // Reorthogonalisation: on request, and by default with the BF16
   // preconditioner, whose rounding makes single-pass Gram-Schmidt lose
   // orthogonality (the cycle minimum is then no longer the true residual).
-  const bool reorth = o->reorth > 0 || (o->reorth == 0 && o->precond == RSFDE_PRECOND_TAU &&
-                                        o->precision == RSFDE_BF16);
+  const bool reorth = o->reorth > 0 || (o->reorth == 0 && tau && o->precision == RSFDE_BF16);
   int total = 0, cycles = 0;
   double beta = 0.0;
   for (;;) {
-    int rc = matvec_impl(P, x, P->w, s);
+    rc = matvec_impl(P, x, P->w, s);
     if (rc) return finish(st, rc, total, cycles, beta, bnorm);
-    {
+    if (left) {
+      rc = precond_impl(P, P->w, nullptr, P->Z, o->precision, s);
+      if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+      ProfScope ps(P, s, kCatResidual, 24.0 * N);
+      CK(launch_residual(P->pb, P->Z, P->V, N, P->rw, P->ks, P->hs_dev, s));
+    } else {
       ProfScope ps(P, s, kCatResidual, 24.0 * N);
       CK(launch_residual(P->b, P->w, P->V, N, P->rw, P->ks, P->hs_dev, s));
     }
@@ -432,23 +549,32 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
       double* vj = P->V + (size_t)j * ld;
       double* zj = P->Z + (size_t)j * ld;
       const double* sig = &P->ks->vscale[j];
-      if (o->precond == RSFDE_PRECOND_TAU) {
-        rc = precond_impl(P, vj, sig, zj, o->precision, s);
+      const double* wv = P->w;  // the vector Arnoldi orthogonalises
+      if (left) {  // w = P_hat^{-1} M v_j
+        rc = matvec_impl(P, vj, P->w, s);
         if (rc) return finish(st, rc, total, cycles, beta, bnorm);
-      } else {
-        ProfScope ps(P, s, kCatOther, 16.0 * N);
-        CK(launch_scale_copy(vj, sig, zj, N, s));
+        rc = precond_impl(P, P->w, sig, zj, o->precision, s);
+        if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+        wv = zj;
+      } else {  // z_j = P_hat^{-1} v_j, w = M z_j
+        if (tau) {
+          rc = precond_impl(P, vj, sig, zj, o->precision, s);
+          if (rc) return finish(st, rc, total, cycles, beta, bnorm);
+        } else {
+          ProfScope ps(P, s, kCatOther, 16.0 * N);
+          CK(launch_scale_copy(vj, sig, zj, N, s));
+        }
+        rc = matvec_impl(P, zj, P->w, s);
+        if (rc) return finish(st, rc, total, cycles, beta, bnorm);
       }
-      rc = matvec_impl(P, zj, P->w, s);
-      if (rc) return finish(st, rc, total, cycles, beta, bnorm);
       double* vnext = P->V + (size_t)(j + 1) * ld;
       {
         ProfScope ps(P, s, kCatMultidot, 8.0 * (j + 2) * (double)N);
-        CK(launch_multidot(P->V, ld, j + 1, P->w, N, P->rw, P->ks, j, false, s));
+        CK(launch_multidot(P->V, ld, j + 1, wv, N, P->rw, P->ks, j, false, s));
       }
       {
         ProfScope ps(P, s, kCatAxpy, 8.0 * (j + 3) * (double)N);
-        CK(launch_axpy_givens(P->V, ld, j + 1, P->w, vnext, N, P->rw, P->ks, j, false, !reorth,
+        CK(launch_axpy_givens(P->V, ld, j + 1, wv, vnext, N, P->rw, P->ks, j, false, !reorth,
                               P->hs_dev, s));
       }
       if (reorth) {  // classical Gram-Schmidt, second pass
@@ -482,11 +608,16 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
         return finish(st, RSFDE_ENONFINITE, total + jmax, cycles, beta, bnorm);
       jc = jmax;
     }
+    const double est = vread(&hs->est[jc - 1]);
     {
       ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
-      CK(launch_update(P->Z, ld, jc, x, N, P->ks, s));
+      CK(launch_update(left ? P->V : P->Z, ld, jc, x, N, P->ks, left, s));
     }
     total += jc;
+    if (left && est <= thresh) {  // stop on the preconditioned estimate
+      CK(hipStreamSynchronize(s));
+      return finish(st, RSFDE_OK, total, cycles, est, bnorm);
+    }
   }
 }
 
@@ -533,7 +664,7 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   if (!(eta > 0.0) || !(dt > 0.0) || !std::isfinite(eta) || !std::isfinite(dt)) return RSFDE_EINVAL;
   if (max_restart <= 0) max_restart = 30;
   if (max_restart > kMaxRestart) return RSFDE_EINVAL;
-  if (n1 > 8191 || n2 > 8191) return RSFDE_EUNSUPPORTED;
+  if (n1 > kMaxN || n2 > kMaxN) return RSFDE_EUNSUPPORTED;
 
   rsfde_plan_s* h = new (std::nothrow) rsfde_plan_s();
   if (!h) return RSFDE_ENOMEM;
@@ -573,6 +704,11 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   P->Lcy = std::max(2, next_pow2(2L * n2));
   P->Ldx = is_pow2(n1 + 1) ? 2 * (n1 + 1) : 0;
   P->Ldy = is_pow2(n2 + 1) ? 2 * (n2 + 1) : 0;
+  if (P->Ldx == 0 || P->Ldy == 0) {  // chirp form in both directions
+    P->Ldx = P->Ldy = 0;
+    P->Lgx = std::max(2, next_pow2(2L * n1 - 1));
+    P->Lgy = std::max(2, next_pow2(2L * n2 - 1));
+  }
 
   const size_t N = P->N, ld = P->ldv;
   const size_t slots = (size_t)(n1 + 1) * (size_t)n2;
@@ -587,6 +723,7 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   AL(P->w, ld);
   AL(P->t, ld);
   AL(P->mu, ld);
+  AL(P->pb, ld);
   double* q = nullptr;
   AL(q, slots);
   P->Q = q;
@@ -611,7 +748,7 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   // Matrix-vector symbols (unit kx, ky).
   if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return fail(RSFDE_ENOMEM);
   if (upload(P, &P->symy, conv_symbol_pos(ty, P->Lcy), s) != hipSuccess) return fail(RSFDE_ENOMEM);
-  for (int L : {P->Lcx, P->Lcy, P->Ldx, P->Ldy})
+  for (int L : {P->Lcx, P->Lcy, P->Ldx, P->Ldy, P->Lgx, P->Lgy})
     if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
 
   // Preconditioner tables (Section 4.1), in the layouts of the three passes.
@@ -643,6 +780,26 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
         upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess ||
         upload(P, &P->mirror, mirror, s) != hipSuccess)
       return fail(RSFDE_ENOMEM);
+  }
+  if (P->Lgx) {  // chirp-form tables
+    const std::vector<double> lx = tau_eigs(tx), ly = tau_eigs(ty);
+    if (upload(P, &P->lamx_n, lx, s) != hipSuccess || upload(P, &P->lamy_n, ly, s) != hipSuccess)
+      return fail(RSFDE_ENOMEM);
+    struct Dir { int n, L; void **ch, **kh; };
+    for (Dir d : {Dir{n1, P->Lgx, P->chx, P->khx}, Dir{n2, P->Lgy, P->chy, P->khy}}) {
+      std::vector<double> ch, kh;
+      chirp_tables(d.n, d.L, ch, kh);
+      const std::vector<float> chf(ch.begin(), ch.end()), khf(kh.begin(), kh.end());
+      double *a = nullptr, *b = nullptr;
+      float *c = nullptr, *e = nullptr;
+      if (upload(P, &a, ch, s) != hipSuccess || upload(P, &b, kh, s) != hipSuccess ||
+          upload(P, &c, chf, s) != hipSuccess || upload(P, &e, khf, s) != hipSuccess)
+        return fail(RSFDE_ENOMEM);
+      d.ch[0] = a;
+      d.kh[0] = b;
+      d.ch[1] = c;
+      d.kh[1] = e;
+    }
   }
   // BF16 / MFMA preconditioner: padded sine matrices, natural-order eigenvalues
   {
@@ -703,9 +860,16 @@ int rsfde_precond_apply(rsfde_plan plan, const double* r, double* z, int32_t pre
 
 int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
                const rsfde_solver_opts* opts, double* u_next, rsfde_stats* stats, void* stream) {
+  return rsfde_step_src(plan, u_prev, u_prev2, f_kind, nullptr, 0.0, opts, u_next, stats, stream);
+}
+
+int rsfde_step_src(rsfde_plan plan, const double* u_prev, const double* u_prev2, int32_t f_kind,
+                   const double* src, double src_scale, const rsfde_solver_opts* opts,
+                   double* u_next, rsfde_stats* stats, void* stream) {
   using namespace rsfde;
   if (!plan || !u_prev || !u_next || u_next == u_prev) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
-  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_CUBIC) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  if (src && (src == u_next || !std::isfinite(src_scale))) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   Plan* P = &plan->p;
   int rc = validate_opts(P, opts);
   if (rc) return finish(stats, rc, 0, 0, 0, 0);
@@ -714,9 +878,9 @@ int rsfde_step(rsfde_plan plan, const double* u_prev, const double* u_prev2, int
   hipStream_t s = pick(P, stream);
   P->hs->flags = 0;
   {
-    ProfScope ps(P, s, kCatRhs, (u_prev2 ? 33.0 : 25.0) * (double)P->N);
-    if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, P->b, u_next, P->N, P->rw, P->hs_dev,
-                   s) != hipSuccess)
+    ProfScope ps(P, s, kCatRhs, (u_prev2 ? 33.0 : 25.0) * (double)P->N + (src ? 8.0 : 0.0) * (double)P->N);
+    if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, src, src_scale, P->b, u_next, P->N,
+                   P->rw, P->hs_dev, s) != hipSuccess)
       return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   }
   return solve_core(P, u_next, opts, stats, s);
@@ -734,8 +898,8 @@ int rsfde_solve(rsfde_plan plan, const double* b, double* x, const rsfde_solver_
   hipStream_t s = pick(P, stream);
   P->hs->flags = 0;
   // copy b into the plan and take its norm (f = 0, dt = 0: b = u, x0 -> scratch)
-  if (launch_rhs(b, nullptr, P->mask, 0.0, RSFDE_F_NONE, P->b, P->t, P->N, P->rw, P->hs_dev, s) !=
-      hipSuccess)
+  if (launch_rhs(b, nullptr, P->mask, 0.0, RSFDE_F_NONE, nullptr, 0.0, P->b, P->t, P->N, P->rw,
+                 P->hs_dev, s) != hipSuccess)
     return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   return solve_core(P, x, opts, stats, s);
 }
@@ -747,7 +911,7 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
   using namespace rsfde;
   if (!plan || !u_prev || !u_cur || !lam_cur || !lam_prev || !dk_dev || lam_prev == lam_cur)
     return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
-  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_CUBIC) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   Plan* P = &plan->p;
   int rc = validate_opts(P, opts);
   if (rc) return finish(stats, rc, 0, 0, 0, 0);
@@ -758,8 +922,8 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
   if (!mu_guess && hipMemsetAsync(mu, 0, P->N * sizeof(double), s) != hipSuccess)
     return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   P->hs->flags = 0;
-  if (launch_rhs(lam_cur, nullptr, P->mask, 0.0, RSFDE_F_NONE, P->b, P->t, P->N, P->rw, P->hs_dev,
-                 s) != hipSuccess)
+  if (launch_rhs(lam_cur, nullptr, P->mask, 0.0, RSFDE_F_NONE, nullptr, 0.0, P->b, P->t, P->N,
+                 P->rw, P->hs_dev, s) != hipSuccess)
     return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   rc = solve_core(P, mu, opts, stats, s);
   if (rc != RSFDE_OK) return rc;

@@ -90,13 +90,21 @@ class RsfdePlan:
         L.rsfde_precond_apply(self.handle, r, z, precision)
         return z
 
-    def step(self, u_prev, u_prev2, f_kind, opts, u_next=None, check=True):
+    def step(self, u_prev, u_prev2, f_kind, opts, u_next=None, check=True, src=None,
+             src_scale=1.0):
+        """One implicit step; with `src` (a field [n2][n1]) the right-hand side
+        gains dt * mask * src_scale * src (rsfde_step_src)."""
         u_next = self.empty() if u_next is None else u_next
         L._check_vec(u_prev, self.N, "u_prev")
         if u_prev2 is not None:
             L._check_vec(u_prev2, self.N, "u_prev2")
         L._check_vec(u_next, self.N, "u_next")
-        st = L.rsfde_step(self.handle, u_prev, u_prev2, f_kind, opts, u_next, check=check)
+        if src is None:
+            st = L.rsfde_step(self.handle, u_prev, u_prev2, f_kind, opts, u_next, check=check)
+        else:
+            L._check_vec(src, self.N, "src")
+            st = L.rsfde_step_src(self.handle, u_prev, u_prev2, f_kind, src, src_scale, opts,
+                                  u_next, check=check)
         return u_next, StepStats(st.iters, st.restarts, st.relres, st.status)
 
     def solve(self, b, x, opts, check=True):
@@ -116,9 +124,11 @@ class RsfdePlan:
                                   mu, dk)
         return StepStats(st.iters, st.restarts, st.relres, st.status)
 
-    def march(self, u0, m, f_kind, opts, keep: Optional[List[int]] = None):
+    def march(self, u0, m, f_kind, opts, keep: Optional[List[int]] = None, src=None,
+              src_scale=None):
         """Run m implicit steps from u0 (flat FP64 tensor).  Returns (u^m, iters per
-        step, {k: u^k for k in keep})."""
+        step, {k: u^k for k in keep}).  src / src_scale(k): optional source field
+        and its factor at step k (evaluated at t_{k-1})."""
         L._check_vec(u0, self.N, "u0")
         bufs = [u0.clone(), self.empty(), self.empty()]
         cur, prev = 0, None
@@ -129,7 +139,8 @@ class RsfdePlan:
         for k in range(1, m + 1):
             nxt = [i for i in range(3) if i != cur and i != prev][0]
             _, st = self.step(bufs[cur], None if prev is None else bufs[prev], f_kind, opts,
-                              bufs[nxt])
+                              bufs[nxt], src=src,
+                              src_scale=1.0 if src_scale is None else src_scale(k))
             iters.append(st.iters)
             prev, cur = cur, nxt
             if keep and k in keep:

@@ -1,0 +1,161 @@
+"""Grids whose n + 1 is not a power of two, the paper's stopping rule (left
+preconditioning) and the paper's own workload, Example 1 of Section 5, on the
+HIP path.
+
+* preconditioner, chirp form: whole output against the oracle's dense DST
+  (small grids) or library DST (larger), 2-norm relative to the input (the
+  operator has 2-norm <= 1): 1e-13 (FP64 internals), 1e-5 (FP32 internals);
+* Example 1 in paper mode (GMRES(20), tol 1e-8, left preconditioning,
+  x0 = 2u^{k-1} - u^{k-2}): mean iterations per step within 0.02 of the values
+  printed in Tables 1 and 2, errors within 3 %, penalty-region values of
+  Table 3 to 2e-4 relative;
+* first-order convergence in h and dt (Section 3) at n = 128, 256, 512.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from workloads.configs import domain_mask, _ellipse, example1_workload, make_config
+
+pytestmark = pytest.mark.gpu
+
+rsfde = pytest.importorskip("paper_2102_11576_amd")
+from paper_2102_11576_amd import RsfdePlan, make_opts  # noqa: E402
+
+DEV = "cuda:0"
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV).reshape(-1)
+
+
+def _problem(n1, n2):
+    w = make_config("c2", n=max(n1, n2))
+    box = (0.0, 1.0, 0.0, 1.2)
+    mask = domain_mask(n1, n2, box, _ellipse(0.5, 0.6, 0.42, 0.5, 10.0))
+    return O.Problem(n1, n2, box, w.alpha1, w.alpha2, 1.1, 0.7, w.eta, 1.0 / 64, mask)
+
+
+def _plan(p, max_restart=30):
+    return RsfdePlan(p.n1, p.n2, p.box, p.alpha1, p.alpha2, p.kx, p.ky, torch.as_tensor(p.mask),
+                     p.eta, p.dt, max_restart)
+
+
+CHIRP_SHAPES = [(1, 2), (2, 2), (4, 5), (31, 20), (32, 32), (33, 20), (64, 64), (100, 37),
+                (20, 130), (300, 200)]
+
+
+@pytest.mark.parametrize("n1,n2", CHIRP_SHAPES)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+def test_chirp_precond_parity(n1, n2, precision, tol):
+    p = _problem(n1, n2)
+    V = np.random.default_rng(n1 * 7 + n2).standard_normal((n2, n1))
+    ref = O.precond_apply(p, V) if n1 * n2 <= 4096 else O.precond_apply_fft(p, V)
+    with _plan(p) as pl:
+        out = pl.precond(_t(V), precision=precision).cpu().numpy().reshape(n2, n1)
+    assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(V)
+
+
+def test_chirp_precond_large_and_maximum_size():
+    """n = 1000 x 999 (convolution length 2048) and the largest grid, 4096^2
+    (length 8192), against the library DST of the oracle."""
+    for n1, n2 in ((1000, 999), (4096, 4096)):
+        p = _problem(n1, n2)
+        V = np.random.default_rng(n1).standard_normal((n2, n1))
+        ref = O.precond_apply_fft(p, V)
+        with _plan(p, 8) as pl:
+            out = pl.precond(_t(V), precision="fp64").cpu().numpy().reshape(n2, n1)
+        assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(V), (n1, n2)
+
+
+def test_nonpow2_step_matches_lu_both_sides():
+    """One FGMRES step and one paper-mode step at 20 x 20 (chirp preconditioner)
+    against the dense LU solve of the same step."""
+    w = make_config("c4", n=20, m=2)
+    p = O.problem_from_workload(w)
+    ref = O.march_lu(p, w.u0, w.m, w.f_kind)
+    with RsfdePlan.from_workload(w) as pl:
+        for side in ("right", "left"):
+            u, _, _ = pl.march(_t(w.u0), w.m, w.f_kind, make_opts(30, 10000, 1e-13, side=side))
+            u = u.cpu().numpy().reshape(w.n2, w.n1)
+            assert np.abs(u - ref).max() / np.abs(ref).max() <= 1e-10, side
+
+
+def _ex1_gpu(n, kx, precond="tau", side="left", reorth=0, **kw):
+    w = example1_workload(n, kx, **kw)
+    dt = w.T / w.m
+    with RsfdePlan.from_workload(w) as pl:
+        u, iters, _ = pl.march(_t(w.u0), w.m, w.f_kind,
+                               make_opts(w.restart, 10000, w.tol, "fp64", precond, reorth, side),
+                               src=_t(w.extra["src"]),
+                               src_scale=lambda k: math.exp(-(k - 1) * dt))
+        u = u.cpu().numpy().reshape(n, n)
+    ue = math.exp(-w.T) * w.extra["exact0"]
+    inside = w.mask.astype(bool)
+    err = np.abs(ue - u)[inside].max() / np.abs(ue)[inside].max()
+    pen = np.abs(u[~inside]).max()
+    return float(err), float(np.mean(iters)), u, float(pen), iters
+
+
+@pytest.mark.parametrize("row", GOLD["table1"]["rows"], ids=lambda r: f"kx{r['kx']}-n{r['n1']}")
+def test_table1_paper_mode(row):
+    err, it, _, _, _ = _ex1_gpu(row["n1"], row["kx"])
+    assert abs(it - row["pgmres_iter"]) <= 0.02, (it, row)
+    assert err == pytest.approx(row["gmres_err"], rel=0.03)
+
+
+@pytest.mark.parametrize("row", [r for r in GOLD["table1"]["rows"] if r["kx"] == 1.0],
+                         ids=lambda r: f"n{r['n1']}")
+def test_table1_unpreconditioned(row):
+    _, it, _, _, _ = _ex1_gpu(row["n1"], row["kx"], precond="none", reorth=1)
+    assert abs(it - row["gmres_iter"]) <= 0.02, (it, row)
+
+
+@pytest.mark.parametrize("row", GOLD["table2"]["rows"], ids=lambda r: f"n{r['n1']}")
+def test_table2_long_time(row):
+    n = row["n1"]
+    err, it, _, _, _ = _ex1_gpu(n, 1.0, T=10.0, m=10 * n)
+    assert abs(it - row["iter"]) <= 0.02, (it, row)
+    assert err == pytest.approx(row["err"], rel=0.03)
+
+
+@pytest.mark.parametrize("row", GOLD["table3"]["rows"], ids=lambda r: f"n{r['n1']}-eta{r['eta']}")
+def test_table3_penalty_region(row):
+    _, _, _, pen, _ = _ex1_gpu(row["n1"], 1e-4, eta=row["eta"])
+    assert pen == pytest.approx(row["pen"], rel=2e-4)
+
+
+def test_paper_mode_matches_oracle_step_by_step():
+    """Same algorithm on both sides (left GMRES(20), paper stopping rule): the
+    iteration count of every step agrees and the solutions agree to far below tol."""
+    w = example1_workload(32, 1.0)
+    err_o, _, u_o, _ = O.example1_march(w, side="left")
+    p = O.problem_from_workload(w)
+    g0 = w.extra["src"]
+    _, it_o = O.march_gmres(p, w.u0, w.m, O.F_NONE, w.restart, w.tol, side="left",
+                            f_values_fn=lambda km1, u: -u + math.exp(-km1 * p.dt) * g0)
+    err_g, _, u_g, _, it_g = _ex1_gpu(32, 1.0)
+    assert it_g == it_o
+    assert np.abs(u_g - u_o).max() <= 1e-10 * np.abs(u_o).max()
+    assert err_g == pytest.approx(err_o, rel=1e-6)
+
+
+def test_first_order_convergence_at_larger_n():
+    """Errors halve as h and dt halve (Section 3), n = 128, 256, 512 (chirp-form
+    preconditioner, right and left modes agree to the solver tolerance)."""
+    errs = []
+    for n in (128, 256, 512):
+        err, it, _, _, _ = _ex1_gpu(n, 1.0)
+        errs.append(err)
+        assert it < 8, (n, it)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.6 < r1 < 2.4 and 1.6 < r2 < 2.4, errs
+    err_r, _, _, _, _ = _ex1_gpu(256, 1.0, side="right")
+    assert err_r == pytest.approx(errs[1], rel=1e-3)

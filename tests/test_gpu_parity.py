@@ -118,18 +118,16 @@ def test_iteration_counts_match_oracle_gmres(name, n):
 
 
 def test_unpreconditioned_and_nonpow2_grid():
-    """n+1 not a power of two: matvec works; GMRES without preconditioner matches LU."""
+    """n+1 not a power of two: plain GMRES and the chirp-form preconditioner both
+    match LU."""
     w = make_config("c4", n=20, m=2)
     p = O.problem_from_workload(w)
     ref = O.march_lu(p, w.u0, w.m, w.f_kind)
     with RsfdePlan.from_workload(w) as pl:
-        u, _, _ = pl.march(_t(w.u0), w.m, w.f_kind,
-                           make_opts(30, 100000, 1e-12, precond="none"))
-        u = u.cpu().numpy().reshape(w.n2, w.n1)
-        with pytest.raises(rsfde.RsfdeError) as ei:
-            pl.step(_t(w.u0), None, w.f_kind, make_opts(30, 100, 1e-8))
-        assert ei.value.code == rsfde._lib.RSFDE_EUNSUPPORTED
-    assert np.abs(u - ref).max() / np.abs(ref).max() <= 1e-10
+        for pc in ("none", "tau"):
+            u, _, _ = pl.march(_t(w.u0), w.m, w.f_kind, make_opts(30, 100000, 1e-12, precond=pc))
+            u = u.cpu().numpy().reshape(w.n2, w.n1)
+            assert np.abs(u - ref).max() / np.abs(ref).max() <= 1e-10, pc
 
 
 def test_error_paths():

@@ -102,3 +102,21 @@ def test_stability_bound():
     ub = O.march_lu(p, w.u0 + d0, w.m, w.f_kind)
     c2 = 1.0 + 2.0 * max(np.abs(w.u0).max(), 1.0)   # Lipschitz constant of u(1-u) on the range
     assert np.abs(ua - ub).max() <= (1 + p.dt * c2) ** w.m * np.abs(d0).max()
+
+
+def test_example1_source_is_the_scheme_consistent_fractional_term():
+    """The Example-1 source field g0 (an input field) equals -(kx R_x + ky R_y) u_e at
+    t = 0.  The GL operator of Section 2 applied to u_e approximates dt (kx R_x + ky R_y)
+    u_e, so A u_e / dt + g0 -> 0 as h -> 0 (in the 2-norm over the domain; the
+    boundary singularity s^{2-alpha} slows the max-norm).  A dropped term, a wrong
+    sign or power in g0 leaves an O(1) remainder."""
+    rel = []
+    for n in (63, 127, 255):
+        w = example1_workload(n, 1.0)
+        p = O.problem_from_workload(w)
+        e0, g0 = w.extra["exact0"], w.extra["src"]
+        Ae = e0 - O.matvec_fast(p, e0)   # M e0 = e0 - A e0 (e0 = 0 in the penalty region)
+        inside = w.mask.astype(bool)
+        rel.append(np.linalg.norm((Ae / p.dt + g0)[inside]) / np.linalg.norm(g0[inside]))
+    assert rel[-1] < 0.012, rel
+    assert rel[0] / rel[1] > 1.5 and rel[1] / rel[2] > 1.5, rel

@@ -32,8 +32,10 @@ F_NONE = 0       # f(u) = 0
 F_LOGISTIC = 1   # f(u) = u (1 - u)
 F_SIN = 2        # f(u) = sin(u)
 F_CUBIC = 3      # f(u) = u - u^3
+F_DECAY = 4      # f(u) = -u (Example 1, with a source field)
 
-F_KIND_NAMES = {F_NONE: "0", F_LOGISTIC: "u(1-u)", F_SIN: "sin(u)", F_CUBIC: "u-u^3"}
+F_KIND_NAMES = {F_NONE: "0", F_LOGISTIC: "u(1-u)", F_SIN: "sin(u)", F_CUBIC: "u-u^3",
+                F_DECAY: "-u"}
 
 
 @dataclass
@@ -211,6 +213,11 @@ def fd_direction(N_shape, i: int):
 
 def example1_workload(n: int, kx: float, eta: float = 1e-5, T: float = 1.0,
                       m: Optional[int] = None, a: float = 2.0, b: float = 1.0) -> Workload:
+    """Example 1 of Section 5: ellipse (a, b) inscribed in (0, 2a) x (0, 2b),
+    alpha = (1.4, 1.7), kx = ky, n1 = n2 = n, m = n steps by default, GMRES(20),
+    tol 1e-8.  f = -u + e^{-t} g0 (F_DECAY plus the field extra["src"] = g0);
+    extra["exact0"] = u_e at t = 0 (u_e(t) = e^{-t} exact0)."""
+    from .example1 import example1_exact, example1_source_field
     box = (0.0, 2.0 * a, 0.0, 2.0 * b)
     shape = _ellipse(a, b, a, b)
     mask = domain_mask(n, n, box, shape)
@@ -218,5 +225,7 @@ def example1_workload(n: int, kx: float, eta: float = 1e-5, T: float = 1.0,
     X, Y = np.meshgrid(x, y)
     u0 = ((X - a) ** 2 / a ** 2 + (Y - b) ** 2 / b ** 2 - 1.0) ** 2 * mask
     steps = (n if m is None else m)
-    return Workload("example1", n, n, box, 1.4, 1.7, kx, kx, eta, T, steps, F_NONE,
-                    20, 1e-8, mask, u0, extra={"a": a, "b": b})
+    src = example1_source_field(X, Y, 1.4, 1.7, kx, kx, a, b)
+    return Workload("example1", n, n, box, 1.4, 1.7, kx, kx, eta, T, steps, F_DECAY,
+                    20, 1e-8, mask, u0,
+                    extra={"a": a, "b": b, "src": src, "exact0": example1_exact(X, Y, 0.0, a, b)})
