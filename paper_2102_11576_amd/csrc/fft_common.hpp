@@ -11,36 +11,86 @@ namespace rsfde {
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 constexpr int lds_len(int L) { return L + (L >> 4) + 1; }
 
+// LDS slots of a stage layout.  For most stages the slot of register e is
+// slot(tau, 0) + delta(e) with delta independent of the thread (checked here
+// at compile time over all threads): the exchange then addresses LDS through
+// one base register and immediate offsets instead of one address register per
+// point, which keeps the FFT kernels' register footprint low.
+template <class F, int t>
+struct LdsLayout {
+  static constexpr int pad(int p) { return p + (p >> 4); }
+  static constexpr int delta(int e) { return pad(F::pos(t, 0, e)) - pad(F::pos(t, 0, 0)); }
+  static constexpr bool check() {
+    for (int tau = 0; tau < F::TPF; ++tau)
+      for (int e = 0; e < F::PP; ++e)
+        if (pad(F::pos(t, tau, e)) - pad(F::pos(t, tau, 0)) != delta(e)) return false;
+    return true;
+  }
+  static constexpr bool linear = check();
+};
+
+template <typename T, class F, int t>
+__device__ __forceinline__ void lds_put(const cpx<T>* reg, int tau, T* lds, bool im) {
+  using LL = LdsLayout<F, t>;
+  if constexpr (LL::linear) {
+    T* b = lds + lds_pad(F::pos(t, tau, 0));
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      b[LL::delta(e)] = im ? reg[e].im : reg[e].re;
+    });
+  } else {
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      lds[lds_pad(F::pos(t, tau, e))] = im ? reg[e].im : reg[e].re;
+    });
+  }
+}
+
+template <typename T, class F, int t>
+__device__ __forceinline__ void lds_get(cpx<T>* reg, int tau, const T* lds, bool im) {
+  using LL = LdsLayout<F, t>;
+  if constexpr (LL::linear) {
+    const T* b = lds + lds_pad(F::pos(t, tau, 0));
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      (im ? reg[e].im : reg[e].re) = b[LL::delta(e)];
+    });
+  } else {
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      (im ? reg[e].im : reg[e].re) = lds[lds_pad(F::pos(t, tau, e))];
+    });
+  }
+}
+
 // Exchange registers between stage layouts through this FFT's LDS region.
 // Real and imaginary parts go through the same region one after the other so
 // that the region holds only L scalars.
 template <typename T, class F, int TF, int TT>
 __device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds) {
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    lds[lds_pad(F::pos(TF, tau, e))] = reg[e].re;
-  });
+  lds_put<T, F, TF>(reg, tau, lds, false);
   __syncthreads();
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    reg[e].re = lds[lds_pad(F::pos(TT, tau, e))];
-  });
+  lds_get<T, F, TT>(reg, tau, lds, false);
   __syncthreads();
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    lds[lds_pad(F::pos(TF, tau, e))] = reg[e].im;
-  });
+  lds_put<T, F, TF>(reg, tau, lds, true);
   __syncthreads();
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    reg[e].im = lds[lds_pad(F::pos(TT, tau, e))];
-  });
+  lds_get<T, F, TT>(reg, tau, lds, true);
   __syncthreads();
+}
+
+// Forces the values of all registers to be computed here.  Without it the
+// compiler sinks the last butterfly of a sweep into the (conditional) stores
+// or pointwise products that follow, which keeps the whole butterfly tree
+// live and costs a wave of occupancy.
+template <typename T, int N>
+__device__ __forceinline__ void materialize(cpx<T>* r) {
+#pragma unroll
+  for (int e = 0; e < N; ++e) asm volatile("" : "+v"(r[e].re), "+v"(r[e].im));
 }
 
 // Forward DIF sweep: natural order (stage-0 positions) in, digit-reversed
 // spectrum (last-stage positions) out.
-template <typename T, class F>
+template <typename T, class F, bool MAT = true>
 __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
@@ -48,10 +98,11 @@ __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* 
     F::template dif_stage<T, t>(reg, tau, tw);
     if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1>(reg, tau, lds);
   });
+  if constexpr (MAT) materialize<T, F::PP>(reg);
 }
 
 // Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order out.
-template <typename T, class F>
+template <typename T, class F, bool MAT = true>
 __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
@@ -59,6 +110,7 @@ __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* 
     F::template dit_stage<T, t>(reg, tau, tw);
     if constexpr (t > 0) lds_exchange<T, F, t, t - 1>(reg, tau, lds);
   });
+  if constexpr (MAT) materialize<T, F::PP>(reg);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap the block

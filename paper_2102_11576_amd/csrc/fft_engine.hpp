@@ -245,7 +245,7 @@ struct Fft {
   static constexpr int blocklen(int t) { return L >> (t * LOGP); }
   static constexpr int stride(int t) { return blocklen(t) / radix(t); }
 
-  static RS_HD int pos(int t, int tau, int e) {
+  static constexpr RS_HD int pos(int t, int tau, int e) {
     const int R = radix(t);
     const int u = e / R, m = e % R;
     const int beta = tau + u * TPF;

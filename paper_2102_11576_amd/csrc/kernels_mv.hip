@@ -26,7 +26,7 @@ struct MvCfg {
 // Row pass.  Block = BR FFTs, FFT b handles rows 2*pair and 2*pair+1.
 // --------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(MvCfg<L>::THR_R) void k_mv_rows(
+__global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_rows(
     const double* __restrict__ z, const uint8_t* __restrict__ mask, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
     double coef, double dpen, int mode) {
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) void k_mv_rows(
 // several rows at once.
 // --------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(MvCfg<L>::THR_C) void k_mv_cols(
+__global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_cols(
     const double* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
     double coef, int mode) {

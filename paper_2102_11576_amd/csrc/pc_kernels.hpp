@@ -121,7 +121,8 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
   });
   T* my = lds + b * lds_len(L);
-  fft_forward<T, F>(reg, tau, tw, my);
+  // (no register materialisation between the sweeps here: it measured slower)
+  fft_forward<T, F, false>(reg, tau, tw, my);
   // spectrum = 2 rho_b - 2i rho_a; keep rho_b for the second column
   const T lxa = valid ? kx * lamx_slot[ca] : (T)0;
   const T lxb = valid ? kx * lamx_slot[cb] : (T)0;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].re = r * e1;
     reg[e].im = -r * e2;
   });
-  fft_inverse<T, F>(reg, tau, tw, my);
+  fft_inverse<T, F, false>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].re = r * e1;
     reg[e].im = -r * e2;
   });
-  fft_inverse<T, F>(reg, tau, tw2, my);
+  fft_inverse<T, F, false>(reg, tau, tw2, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
