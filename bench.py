@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--mode", choices=["march", "kernels"], default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--sstep", type=int, default=8,
+                    help="GMRES form of the timed march: s >= 2 the s-step block form, "
+                         "0 one Arnoldi vector per step (both are reported)")
     return ap.parse_args()
 
 
@@ -73,7 +76,7 @@ def kernel_mode(args):
             plan.precond(u0, y, prec)
         torch.cuda.synchronize()
         log(f"precond {prec} x{args.reps}")
-    plan.march(u0, 2, w.f_kind, make_opts(w.restart, 100000, w.tol))
+    plan.march(u0, 2, w.f_kind, make_opts(w.restart, 100000, w.tol, sstep=args.sstep))
     torch.cuda.synchronize()
     log("2 implicit steps")
     plan.close()
@@ -122,7 +125,7 @@ def cpu_baseline(w, gpu_iters_per_step):
     }
 
 
-def adjoint_rate(log):
+def adjoint_rate(log, sstep=0):
     """Adjoint gradients per second on the differentiation workload: 511^2 disk
     r=0.4, alpha=(1.3,1.6), 32 FP64 steps, L = ||u(T) - u_tgt||^2 with u_tgt
     marched at (kx, ky) = (1.2, 0.8); one gradient = forward march with
@@ -137,10 +140,11 @@ def adjoint_rate(log):
     w = make_config("c4")
     dev = torch.device("cuda:0")
     res = {"workload": "c4: 511x511 disk r=0.4, alpha=(1.3,1.6), 32 steps, GMRES(30) tol 1e-8 "
-                       "(FD check at tol 1e-12), loss ||u(T)-u_tgt||^2, grads w.r.t. u0, kx, ky"}
+                       "(FD check at tol 1e-12), loss ||u(T)-u_tgt||^2, grads w.r.t. u0, kx, ky",
+           "gmres_form": f"s-step (s={sstep})" if sstep >= 2 else "one vector per step"}
     with RsfdePlan.from_workload(w, device=dev) as pl:
         u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
-        opts = make_opts(w.restart, 100000, w.tol)
+        opts = make_opts(w.restart, 100000, w.tol, sstep=sstep)
         pl.set_coeffs(*w.extra["target_k"])
         u_tgt = pl.march(u0, w.m, w.f_kind, make_opts(w.restart, 100000, 1e-12))[0].clone()
 
@@ -162,7 +166,7 @@ def adjoint_rate(log):
         dt = (time.perf_counter() - t0) / reps
         res.update({"grads_per_s": 1.0 / dt, "s_per_grad": dt})
         log(f"adjoint: {dt:.3f} s per gradient (forward + reverse sweep)")
-        tight = make_opts(w.restart, 100000, 1e-12)
+        tight = make_opts(w.restart, 100000, 1e-12, sstep=sstep)
         g0, gkx, gky = grad(tight)
 
         def loss(uu0, kx, ky):
@@ -226,8 +230,8 @@ def main():
     plan = RsfdePlan.from_workload(w, device=dev)
     u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
 
-    def timed_march(precision, steps, profile=False):
-        opts = make_opts(w.restart, 100000, w.tol, precision)
+    def timed_march(precision, steps, profile=False, sstep=args.sstep):
+        opts = make_opts(w.restart, 100000, w.tol, precision, sstep=sstep)
         if W > 0:
             plan.march(u0, min(W, w.m), w.f_kind, opts)
         torch.cuda.synchronize()
@@ -247,7 +251,8 @@ def main():
     log(f"workload {w.name} {w.n1}x{w.n2}, timing {K} steps after {W} warm-up steps")
     u64, it64, t64, _ = timed_march("fp64", K)
     value = w.N * K / t64
-    log(f"fp64: {1e3 * t64 / K:.2f} ms/step, {np.mean(it64):.1f} iterations/step")
+    form = f"s-step (s={args.sstep})" if args.sstep >= 2 else "one vector per step"
+    log(f"fp64, {form}: {1e3 * t64 / K:.2f} ms/step, {np.mean(it64):.1f} iterations/step")
     out = {
         "metric": METRIC,
         "value": value,
@@ -267,10 +272,18 @@ def main():
                          f"to T={w.T}, f=sin(u), 8 seeded Gaussian bumps, FGMRES({w.restart}) tol {w.tol}"),
             "n1": w.n1, "n2": w.n2, "time_steps_total": w.m, "restart": w.restart, "tol": w.tol,
             "preconditioner": "fp64",
+            "gmres_form": form,
         },
         "gmres_iters_per_step": float(np.mean(it64)),
         "gmres_iters": it64,
     }
+    if args.sstep >= 2:
+        u1, it1, t1, _ = timed_march("fp64", K, sstep=0)
+        log(f"fp64, one vector per step: {1e3 * t1 / K:.2f} ms/step, {np.mean(it1):.1f} iterations/step")
+        out["one_vector_per_step"] = {
+            "value": w.N * K / t1, "ms_per_step": 1e3 * t1 / K,
+            "gmres_iters_per_step": float(np.mean(it1)),
+            "rel_err_inf_vs_sstep": float((u1 - u64).abs().max() / u64.abs().max())}
 
     if not args.no_mixed:
         u32, it32, t32, _ = timed_march("fp32", K)
@@ -281,8 +294,8 @@ def main():
         # vector is amplified by ||M|| ~ 1e5), so the full march is
         # not run here.
         KB = min(2, K)
-        u64b, _, _, _ = timed_march("fp64", KB)
-        ub, itb, tb, profb = timed_march("bf16", KB, profile=not args.no_profile)
+        u64b, _, _, _ = timed_march("fp64", KB, sstep=0)
+        ub, itb, tb, profb = timed_march("bf16", KB, profile=not args.no_profile, sstep=0)
         log(f"bf16 preconditioner ({KB} steps): {1e3 * tb / KB:.2f} ms/step, "
             f"{np.mean(itb):.1f} iterations/step")
         db = float((ub - u64b).abs().max() / u64b.abs().max())
@@ -325,7 +338,7 @@ def main():
         out["profiled_ms_per_step"] = 1e3 * tprof / K
 
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_rate(log)
+        out["adjoint"] = adjoint_rate(log, args.sstep)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")

@@ -85,6 +85,12 @@ typedef struct {
                         0 = default: two with the BF16 preconditioner, else one */
   int32_t side;      /* RSFDE_RIGHT (default) or RSFDE_LEFT; with RSFDE_PRECOND_NONE
                         both are plain GMRES */
+  int32_t sstep;     /* 0 or 1: one Arnoldi vector per step (classical Gram-Schmidt).
+                        2..16: s-step form (right side, sine-transform preconditioner):
+                        s directions u_{i+1} = (M P^{-1} - I) u_i per block, orthogonalised
+                        together (block Gram-Schmidt + Cholesky QR); same Krylov space,
+                        about s times less basis traffic.  Grids with N < 4096 use the
+                        one-vector form. */
 } rsfde_solver_opts;
 
 typedef struct {

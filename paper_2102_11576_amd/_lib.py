@@ -40,7 +40,7 @@ class rsfde_grid(C.Structure):
 class rsfde_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("reorth", C.c_int32),
-                ("side", C.c_int32)]
+                ("side", C.c_int32), ("sstep", C.c_int32)]
 
 
 class rsfde_stats(C.Structure):
@@ -132,15 +132,17 @@ def _raise(rc, where):
 
 
 def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0,
-              side="right"):
+              side="right", sstep=0):
     """reorth: 1 = two Gram-Schmidt passes, -1 = one, 0 = two only with BF16.
     side: "right" (flexible GMRES, true-residual stop) or "left" (the stopping
-    rule of the paper's experiments)."""
+    rule of the paper's experiments).  sstep: 0/1 one Arnoldi vector per step,
+    s >= 2 the s-step block form."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
         if isinstance(precond, str) else int(precond)
     sd = {"right": RSFDE_RIGHT, "left": RSFDE_LEFT}[side] if isinstance(side, str) else int(side)
-    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), sd)
+    return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), sd,
+                             int(sstep))
 
 
 def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30, stream=None):

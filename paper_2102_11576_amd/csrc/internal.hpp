@@ -49,12 +49,14 @@ struct RedWork {
 
 // ----------------------------- FFT kernels --------------------------------
 // Row pass of the matrix-vector product:
-//   out = coef * (C_x z) + diag * z, diag = (mode==0) ? 1 + dpen (1 - mask) : 0,
+//   out = coef * (C_x z) + diag * z - theta * sub,
+//   diag = (mode==0) ? 1 + dpen (1 - mask) : 0 (sub = NULL: no shift term),
 // where C_x is the Toeplitz matrix whose circulant embedding of length L has
 // the symbol `sym` (already divided by L, stored in register-position order).
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2,
-                          double coef, double dpen, int mode, hipStream_t s);
+                          double coef, double dpen, int mode, hipStream_t s,
+                          const double* sub = nullptr, double theta = 0.0);
 // Column pass: out = coef * (C_y z) + (mode==0 ? t : 0).
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2,
@@ -127,6 +129,20 @@ hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double*
 // vscale[i] (Z = the unnormalised basis V: left preconditioning).
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
                          KrylovState* ks, bool scaled, hipStream_t s);
+// x += sum_{i<jc} c_i Z_i with the coefficients c given (device array).
+hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
+                              const double* c, hipStream_t s);
+
+// s-step blocks (krylov_block.hip).  G (pinned, device-visible, [nr][16]) =
+// [V_0 .. V_{nr-1}]^T [V_{m1} .. V_{m1+s-1}]; gpart holds
+// 16 * 16 * kGramMaxTiles * kGramBlocks partial sums.
+constexpr int kGramBlocks = 512;
+constexpr int kGramMaxTiles = 5;  // up to 80 Gram rows
+hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
+                        double* gpart, double* G_host_dev, hipStream_t st);
+// V_{m1..m1+s-1} <- (V_{m1..} - V_{0..nq-1} C) R^{-1}; coef = C [nq][s] then R^{-1} [s][s].
+hipError_t launch_bupd(double* V, size_t ld, int nq, int m1, int s, size_t N, const double* coef,
+                       hipStream_t st);
 hipError_t launch_scale_copy(const double* v, const double* sig, double* z, size_t N,
                              hipStream_t s);
 hipError_t launch_adj_lambda(const double* mu, const double* u_prev, const uint8_t* mask,

@@ -29,7 +29,7 @@ template <int L>
 __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_rows(
     const double* __restrict__ z, const uint8_t* __restrict__ mask, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
-    double coef, double dpen, int mode) {
+    double coef, double dpen, int mode, const double* __restrict__ sub, double theta) {
   using C = MvCfg<L>;
   using F = typename C::F;
   __shared__ double lds[C::BR * lds_len(L)];
@@ -65,12 +65,14 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu
         const size_t i = (size_t)ra * n1 + p;
         double v = reg[e].re;
         if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        if (sub) v -= theta * sub[i];
         out[i] = v;
       }
       if (vb) {
         const size_t i = (size_t)rb * n1 + p;
         double v = reg[e].im;
         if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        if (sub) v -= theta * sub[i];
         out[i] = v;
       }
     }
@@ -132,12 +134,12 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
 template <int L>
 static hipError_t mv_rows_impl(const double* z, const uint8_t* mask, double* out, const double* sym,
                                const void* tw, int n1, int n2, double coef, double dpen, int mode,
-                               hipStream_t s) {
+                               hipStream_t s, const double* sub, double theta) {
   using C = MvCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
   hipLaunchKernelGGL(k_mv_rows<L>, dim3(blocks), dim3(C::THR_R), 0, s, z, mask, out, sym,
-                     (const cpx<double>*)tw, n1, n2, coef, dpen, mode);
+                     (const cpx<double>*)tw, n1, n2, coef, dpen, mode, sub, theta);
   return hipGetLastError();
 }
 
@@ -157,11 +159,11 @@ static hipError_t mv_cols_impl(const double* z, const double* t, double* out, co
 
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,
-                          double dpen, int mode, hipStream_t s) {
+                          double dpen, int mode, hipStream_t s, const double* sub, double theta) {
   switch (L) {
 #define X(LL) \
   case LL:    \
-    return mv_rows_impl<LL>(z, mask, out, sym, tw, n1, n2, coef, dpen, mode, s);
+    return mv_rows_impl<LL>(z, mask, out, sym, tw, n1, n2, coef, dpen, mode, s, sub, theta);
     RSFDE_L_CASES(X)
 #undef X
     default:

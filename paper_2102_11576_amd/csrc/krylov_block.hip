@@ -1,0 +1,219 @@
+// Block kernels of the s-step form of the restarted GMRES (Section 5 of the
+// paper runs GMRES; its orthogonalisation scheme is not fixed there).  One
+// block of s Krylov directions U = [u_1 .. u_s] (u_{i+1} = (M P^{-1} - theta) u_i)
+// is orthogonalised against the m+1 orthonormal basis vectors Q in two passes
+// over the basis instead of 2s:
+//   gram:   G = [Q U]^T U   (projections C = Q^T U and U^T U in one pass: a
+//           tall-skinny FP64 contraction on the matrix cores)
+//   update: U <- (U - Q C) R^{-1}, R = chol(U^T U - C^T C)  (R from the host)
+// Q and U are adjacent slots of the basis array V, so [Q U] is one strided
+// matrix.  Partial sums are per block and added in a fixed order: results are
+// deterministic.
+#include "krylov_common.hpp"
+
+namespace rsfde {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kGramThreads = 256;  // 4 wavefronts
+
+// Partial Gram block: gpart[(r * 16 + c) * kGramBlocks + block] = sum over this
+// block's elements of A[r][e] * U[c][e], r < nr, c < s, with A row r = V + r*ld
+// and U column c = V + (m1 + c)*ld.  NT = number of 16-row tiles (nr <= 16 NT).
+// v_mfma_f64_16x16x4: lane l supplies A[l%16][k] and B[k][l%16] with k = l/16,
+// and holds D[l/16 + 4i][l%16], i < 4.  The K index runs over elements: lane
+// group k takes elements base + 2k and base + 2k + 1 (one 16-byte load per row),
+// the same mapping for A and B.
+template <int NT>
+__global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict__ V, size_t ld,
+                                                        int nr, int m1, int s, size_t N,
+                                                        double* __restrict__ gpart) {
+  __shared__ double red[4][NT][64][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const bool bvalid = i16 < s;
+  const double* brow = V + (size_t)(m1 + (bvalid ? i16 : 0)) * ld;
+  const double* arow[NT];
+  bool avalid[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int r = 16 * t + i16;
+    avalid[t] = r < nr;
+    arow[t] = V + (size_t)(avalid[t] ? r : 0) * ld;
+  }
+  v4d acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const size_t nchunks = N / 8;  // 8 elements per wave step
+  const size_t gw = (size_t)gridDim.x * 4;
+  for (size_t ch = (size_t)blockIdx.x * 4 + wid; ch < nchunks; ch += gw) {
+    const size_t e = ch * 8 + 2 * k4;
+    const double2 b = bvalid ? *reinterpret_cast<const double2*>(brow + e) : double2{0.0, 0.0};
+    double2 a[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      a[t] = avalid[t] ? *reinterpret_cast<const double2*>(arow[t] + e) : double2{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].y, b.y, acc[t], 0, 0, 0);
+    }
+  }
+  // tail (N % 8 elements): block 0, wave 0 only
+  if (blockIdx.x == 0 && wid == 0) {
+    const size_t e0 = nchunks * 8 + 2 * k4;
+    double2 b = {0.0, 0.0};
+    if (bvalid && e0 < N) b.x = brow[e0];
+    if (bvalid && e0 + 1 < N) b.y = brow[e0 + 1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double2 a = {0.0, 0.0};
+      if (avalid[t] && e0 < N) a.x = arow[t][e0];
+      if (avalid[t] && e0 + 1 < N) a.y = arow[t][e0 + 1];
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[wid][t][lane][q] = acc[t][q];
+  __syncthreads();
+  if (wid == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = red[0][t][lane][q] + red[1][t][lane][q] + red[2][t][lane][q] +
+                         red[3][t][lane][q];
+        const int r = 16 * t + k4 + 4 * q, c = i16;
+        if (r < nr && c < s) gpart[(size_t)(r * 16 + c) * kGramBlocks + blockIdx.x] = v;
+      }
+  }
+}
+
+// G[r * 16 + c] = sum of the partials (fixed order), written where the host
+// reads it (pinned, device-visible memory).
+__global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* __restrict__ gpart,
+                                                                 int nr, int s, int nb,
+                                                                 double* G) {
+  const int lane = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < nr * s; p += kFinishThreads / 64) {
+    const int r = p / s, c = p % s;
+    const double* src = gpart + (size_t)(r * 16 + c) * kGramBlocks;
+    double x = 0.0;
+    for (int k = lane; k < nb; k += 64) x += src[k];
+    x = wave_sum(x);
+    if (lane == 0) G[r * 16 + c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __threadfence_system();
+}
+
+// U <- (U - Q C) R^{-1} in place, U = V + m1*ld (S vectors), Q = V (nq vectors).
+// coef: C row-major [nq][S] followed by R^{-1} row-major [S][S] (upper
+// triangular); uniform reads, so they come through the scalar cache.
+template <int S>
+__global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, size_t ld, int nq,
+                                                      int m1, size_t N,
+                                                      const double* __restrict__ coef) {
+  const double* __restrict__ Rinv = coef + (size_t)nq * S;
+  double* U = V + (size_t)m1 * ld;
+  const size_t N2 = N / 2;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double2 y[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) y[k] = reinterpret_cast<const double2*>(U + (size_t)k * ld)[i];
+    int q = 0;
+    for (; q + 4 <= nq; q += 4) {
+      double2 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = reinterpret_cast<const double2*>(V + (size_t)(q + u) * ld)[i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          const double c = coef[(q + u) * S + k];
+          y[k].x -= c * x[u].x;
+          y[k].y -= c * x[u].y;
+        }
+    }
+    for (; q < nq; ++q) {
+      const double2 x = reinterpret_cast<const double2*>(V + (size_t)q * ld)[i];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const double c = coef[q * S + k];
+        y[k].x -= c * x.x;
+        y[k].y -= c * x.y;
+      }
+    }
+#pragma unroll
+    for (int k = S - 1; k >= 0; --k) {  // out_k = sum_{l<=k} y_l Rinv[l][k] (descending: in place)
+      double2 o = {0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l <= k; ++l) {
+        const double r = Rinv[l * S + k];
+        o.x += y[l].x * r;
+        o.y += y[l].y * r;
+      }
+      reinterpret_cast<double2*>(U + (size_t)k * ld)[i] = o;
+    }
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t e = N - 1;
+    double y[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) y[k] = U[(size_t)k * ld + e];
+    for (int q = 0; q < nq; ++q) {
+      const double x = V[(size_t)q * ld + e];
+#pragma unroll
+      for (int k = 0; k < S; ++k) y[k] -= coef[q * S + k] * x;
+    }
+#pragma unroll
+    for (int k = S - 1; k >= 0; --k) {
+      double o = 0.0;
+#pragma unroll
+      for (int l = 0; l <= k; ++l) o += y[l] * Rinv[l * S + k];
+      U[(size_t)k * ld + e] = o;
+    }
+  }
+}
+
+// ------------------------------- launchers --------------------------------
+
+hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
+                        double* gpart, double* G_host_dev, hipStream_t st) {
+  if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
+  int nb = (int)((N / 8 + 4 * 16 - 1) / (4 * 16));  // >= 16 wave steps per wave
+  if (nb < 1) nb = 1;
+  if (nb > kGramBlocks) nb = kGramBlocks;
+  const int nt = (nr + 15) / 16;
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_bgram<1>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 2: hipLaunchKernelGGL(k_bgram<2>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 3: hipLaunchKernelGGL(k_bgram<3>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 4: hipLaunchKernelGGL(k_bgram<4>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 5: hipLaunchKernelGGL(k_bgram<5>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_bgram_finish, dim3(1), dim3(kFinishThreads), 0, st, gpart, nr, s, nb,
+                     G_host_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_bupd(double* V, size_t ld, int nq, int m1, int s, size_t N, const double* coef,
+                       hipStream_t st) {
+  const dim3 g(red_blocks(N)), b(kRedThreads);
+  switch (s) {
+#define X(SS) \
+  case SS: hipLaunchKernelGGL(k_bupd<SS>, g, b, 0, st, V, ld, nq, m1, N, coef); break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rsfde

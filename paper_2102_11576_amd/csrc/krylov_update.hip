@@ -12,9 +12,12 @@ template <int NV>
 __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict__ Z, size_t ldz,
                                                         double* __restrict__ x, size_t N,
                                                         const KrylovState* __restrict__ ks,
-                                                        int v0, int jc, bool scaled) {
+                                                        int v0, int jc, bool scaled,
+                                                        const double* __restrict__ cgiven) {
   __shared__ double y[kMaxRestart];
-  if (threadIdx.x == 0) {
+  if (cgiven) {
+    if (threadIdx.x < NV) y[v0 + threadIdx.x] = cgiven[v0 + threadIdx.x];
+  } else if (threadIdx.x == 0) {
     for (int i = jc - 1; i >= 0; --i) {
       double s = ks->g[i];
       for (int k = i + 1; k < jc; ++k) s -= ks->H[(size_t)k * kLdH + i] * y[k];
@@ -25,7 +28,7 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
   __syncthreads();
   double c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v] * (scaled ? ks->vscale[v0 + v] : 1.0);
+  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v] * (scaled && !cgiven ? ks->vscale[v0 + v] : 1.0);
   const size_t N2 = N / 2;
   double2* x2 = reinterpret_cast<double2*>(x);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2;
@@ -50,11 +53,12 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
 }
 
 using UpdateFn = void (*)(const double*, size_t, double*, size_t, const KrylovState*, int, int,
-                          bool, dim3, hipStream_t);
+                          bool, const double*, dim3, hipStream_t);
 template <int NV>
 static void run_update(const double* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
-                       int v0, int jc, bool scaled, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc, scaled);
+                       int v0, int jc, bool scaled, const double* cg, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc, scaled,
+                     cg);
 }
 template <int... I>
 static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
@@ -68,7 +72,22 @@ hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t 
   if (jc > kMaxRestart) return hipErrorInvalidValue;
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, dim3(red_blocks(N)), s);
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, nullptr,
+                   dim3(red_blocks(N)), s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
+                              const double* c, hipStream_t s) {
+  if (jc <= 0) return hipSuccess;
+  if (jc > kMaxRestart) return hipErrorInvalidValue;
+  for (int v0 = 0; v0 < jc; v0 += kChunk) {
+    const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, nullptr, v0, jc, false, c,
+                   dim3(red_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -115,6 +116,13 @@ struct Plan {
   __bf16* G = nullptr;
   KrylovState* ks = nullptr;
   RedWork rw{nullptr};
+  // s-step blocks: Gram partials, Gram result (pinned, device-visible), update
+  // coefficients (device) and their pinned staging copy
+  double* gpart = nullptr;
+  double* gram_h = nullptr;
+  double* gram_d = nullptr;
+  double* coef_d = nullptr;
+  double* coef_h = nullptr;
   HostStatus* hs = nullptr;      // pinned host memory
   HostStatus* hs_dev = nullptr;  // its device-visible address
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -127,6 +135,7 @@ struct Plan {
     double bytes;
   };
   bool prof_on = false;
+  bool trace = false;  // RSFDE_TRACE=1: s-step block diagnostics on stderr
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   hipEvent_t take_event() {
@@ -143,6 +152,8 @@ struct Plan {
   ~Plan() {
     for (void* p : allocs) (void)hipFree(p);
     if (hs) (void)hipHostFree(hs);
+    if (gram_h) (void)hipHostFree(gram_h);
+    if (coef_h) (void)hipHostFree(coef_h);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& r : prof_recs) {
@@ -170,12 +181,13 @@ hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
 enum ProfCat {
   kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
   kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kCatCdRows, kCatCdCols,
-  kCatCdRowsInv, kNumCats
+  kCatCdRowsInv, kCatGram, kCatBupd, kNumCats
 };
 const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
                                          "pc_rows_inv", "multidot", "axpy_givens", "update",
                                          "residual", "rhs", "other", "pc_gemm_bf16",
-                                         "cd_rows_fwd", "cd_cols", "cd_rows_inv"};
+                                         "cd_rows_fwd", "cd_cols", "cd_rows_inv", "block_gram",
+                                         "block_update"};
 
 // Brackets one kernel launch with timing events when profiling is on.
 struct ProfScope {
@@ -367,12 +379,14 @@ hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
   return hipSuccess;
 }
 
-int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s) {
+// y = M x - theta * sub (sub = NULL: y = M x).
+int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s, const double* sub = nullptr,
+                double theta = 0.0) {
   const double N = (double)P->N;
   {
-    ProfScope ps(P, s, kCatMvRows, 17.0 * N);
+    ProfScope ps(P, s, kCatMvRows, (sub ? 25.0 : 17.0) * N);
     CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
-                      P->dpen, 0, s));
+                      P->dpen, 0, s, sub, theta));
   }
   {
     ProfScope ps(P, s, kCatMvCols, 24.0 * N);
@@ -469,6 +483,11 @@ int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (o->precision < RSFDE_FP64 || o->precision > RSFDE_BF16) return RSFDE_EINVAL;
   if (o->reorth < -1 || o->reorth > 1) return RSFDE_EINVAL;
   if (o->side != RSFDE_RIGHT && o->side != RSFDE_LEFT) return RSFDE_EINVAL;
+  if (o->sstep < 0 || o->sstep > 16) return RSFDE_EINVAL;
+  if (o->sstep >= 2) {
+    if (o->precond != RSFDE_PRECOND_TAU || o->side != RSFDE_RIGHT) return RSFDE_EUNSUPPORTED;
+    if (o->restart + 1 + o->sstep > 16 * kGramMaxTiles) return RSFDE_EUNSUPPORTED;
+  }
   (void)P;
   return RSFDE_OK;
 }
@@ -496,7 +515,11 @@ int finish(rsfde_stats* st, int code, int iters, int restarts, double beta, doub
 //  left (the convention of the experiments of Section 5): Arnoldi on
 //    P_hat^{-1} M, x += V y; stops when the residual estimate of
 //    ||P_hat^{-1}(b - M x)|| is <= tol ||P_hat^{-1} b||.
+int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st,
+                     hipStream_t s);
+
 int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s) {
+  if (o->sstep >= 2 && P->N >= 4096) return solve_core_sstep(P, x, o, st, s);
   const size_t N = P->N, ld = P->ldv;
   volatile HostStatus* hs = P->hs;
   const bool tau = o->precond == RSFDE_PRECOND_TAU;
@@ -621,6 +644,333 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// s-step form of the right-preconditioned restarted GMRES.  Per block of s
+// steps: s preconditioner + matrix-vector applications build the directions
+// u_{i+1} = (M P^{-1} - theta) u_i from u_0 = q_m (theta = 1, the centre of
+// the preconditioned spectrum); one Gram pass G = [Q U]^T U on the matrix
+// cores; on the host C = Q^T U, R = chol(U^T U - C^T C) (a second block pass
+// when that loses too many digits); one update pass U <- (U - Q C) R^{-1}.
+// The Hessenberg columns of the block follow from
+//   (M P^{-1}) Q S_l = Q (S_r) with S the block's coordinates,
+// the Givens rotations and residual estimates are the usual ones (host), and
+// the solution update uses the stored P^{-1} u vectors with coefficients
+// W y, W the triangular map from basis vectors to directions.
+// ---------------------------------------------------------------------------
+
+// Upper-triangular R with R^T R = A (s x s, row-major), column by column.
+// Returns the number of leading pivots accepted: a pivot fails when it is not
+// positive or below rel * A_kk (the direction is numerically dependent on the
+// ones before it, or A = U^T U - C^T C lost it to cancellation).
+int cholesky_upper(const std::vector<double>& A, int n, std::vector<double>& R, double rel) {
+  R.assign((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double d = A[k * n + k];
+    for (int i = 0; i < k; ++i) d -= R[i * n + k] * R[i * n + k];
+    if (!(d > rel * std::fabs(A[k * n + k])) || !std::isfinite(d)) return k;
+    const double rk = std::sqrt(d);
+    R[k * n + k] = rk;
+    for (int j = k + 1; j < n; ++j) {
+      double v = A[k * n + j];
+      for (int i = 0; i < k; ++i) v -= R[i * n + k] * R[i * n + j];
+      R[k * n + j] = v / rk;
+    }
+  }
+  return n;
+}
+
+// Inverse of an upper-triangular n x n matrix (row-major).
+std::vector<double> upper_inverse(const std::vector<double>& R, int n) {
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    X[j * n + j] = 1.0 / R[j * n + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int k = i + 1; k <= j; ++k) v += R[i * n + k] * X[k * n + j];
+      X[i * n + j] = -v / R[i * n + i];
+    }
+  }
+  return X;
+}
+
+// One block projection / Cholesky-QR step on the host from the Gram result:
+// C [nq][ss] (row-major) and R [ss][ss]; returns the number of directions
+// whose pivots were accepted (the leading part of R is valid).
+int block_factor(const double* G, int nq, int ss, std::vector<double>& C, std::vector<double>& R) {
+  C.assign((size_t)nq * ss, 0.0);
+  for (int i = 0; i < nq; ++i)
+    for (int k = 0; k < ss; ++k) C[i * ss + k] = G[i * 16 + k];
+  std::vector<double> A((size_t)ss * ss);
+  for (int a = 0; a < ss; ++a)
+    for (int b = 0; b < ss; ++b) {
+      double v = G[(nq + a) * 16 + b];
+      for (int i = 0; i < nq; ++i) v -= C[i * ss + a] * C[i * ss + b];
+      A[a * ss + b] = v;
+    }
+  for (int a = 0; a < ss; ++a)  // symmetrise
+    for (int b = a + 1; b < ss; ++b) A[a * ss + b] = A[b * ss + a] = 0.5 * (A[a * ss + b] + A[b * ss + a]);
+  return cholesky_upper(A, ss, R, 1e-13);
+}
+
+// Leading k x k part of a row-major n x n matrix, and the first k columns of
+// a row-major [rows][n] matrix.
+std::vector<double> lead_square(const std::vector<double>& A, int n, int k) {
+  std::vector<double> B((size_t)k * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) B[(size_t)i * k + j] = A[(size_t)i * n + j];
+  return B;
+}
+std::vector<double> lead_cols(const std::vector<double>& A, int rows, int n, int k) {
+  std::vector<double> B((size_t)rows * k);
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < k; ++j) B[(size_t)i * k + j] = A[(size_t)i * n + j];
+  return B;
+}
+
+int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s);
+
+// finish() that also reports the count of reorthogonalised / truncated blocks
+int finish_ev(rsfde_stats* st, int events, int code, int iters, int restarts, double beta,
+              double bnorm) {
+  const int rc = finish(st, code, iters, restarts, beta, bnorm);
+  if (st) st->reserved = events;
+  return rc;
+}
+
+int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st,
+                     hipStream_t s) {
+  const size_t N = P->N, ld = P->ldv;
+  volatile HostStatus* hs = P->hs;
+  const int S = o->sstep, RS = o->restart;
+  const double theta = 1.0;
+  CK(hipStreamSynchronize(s));
+  if (vread(&hs->flags) & kFlagNonFinite) return finish_ev(st, 0, RSFDE_ENONFINITE, 0, 0, 0, 0);
+  const double bnorm = vread(&hs->bnorm);
+  if (bnorm == 0.0) {
+    CK(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    CK(hipStreamSynchronize(s));
+    return finish_ev(st, 0, RSFDE_OK, 0, 0, 0.0, 0.0);
+  }
+  const double thresh = o->tol * bnorm;
+  const int LH = RS + 1;                        // leading dimension of H (row-major [row][col])
+  std::vector<double> Hraw((size_t)LH * RS), Hrot((size_t)LH * RS), W((size_t)RS * RS);
+  std::vector<double> cs(RS), sn(RS), g(RS + 1), C, R, C2, R2;
+  int total = 0, cycles = 0, events = 0;
+  double beta = 0.0;
+  for (;;) {
+    int rc = matvec_impl(P, x, P->w, s);
+    if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
+    {
+      ProfScope ps(P, s, kCatResidual, 24.0 * N);
+      CK(launch_residual(P->b, P->w, P->V, N, P->rw, P->ks, P->hs_dev, s));
+    }
+    CK(hipStreamSynchronize(s));
+    if (vread(&hs->flags) & kFlagNonFinite) return finish_ev(st, events, RSFDE_ENONFINITE, total, cycles, beta, bnorm);
+    beta = vread(&hs->beta);
+    if (beta <= thresh) return finish_ev(st, events, RSFDE_OK, total, cycles, beta, bnorm);
+    if (total >= o->max_iters) return finish_ev(st, events, RSFDE_ENOTCONV, total, cycles, beta, bnorm);
+    ++cycles;
+    {  // q_0 = r / beta, stored normalised
+      ProfScope ps(P, s, kCatOther, 16.0 * N);
+      CK(launch_scale_copy(P->V, &P->ks->vscale[0], P->V, N, s));
+    }
+    const int jmax = std::min(RS, o->max_iters - total);
+    std::fill(Hraw.begin(), Hraw.end(), 0.0);
+    std::fill(Hrot.begin(), Hrot.end(), 0.0);
+    std::fill(W.begin(), W.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int m = 0, jc = -1;
+    while (m < jmax) {
+      int ss = std::min(S, jmax - m);
+      W[(size_t)m * RS + m] = 1.0;  // q_m is itself the first direction of the block
+      for (int i = 0; i < ss; ++i) {
+        double* ui = P->V + (size_t)(m + i) * ld;
+        double* zi = P->Z + (size_t)(m + i) * ld;
+        rc = precond_impl(P, ui, nullptr, zi, o->precision, s);
+        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
+        rc = matvec_impl(P, zi, P->V + (size_t)(m + i + 1) * ld, s, ui, theta);
+        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
+      }
+      const int nq = m + 1;
+      int nr = m + 1 + ss;
+      {
+        ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)N);
+        CK(launch_bgram(P->V, ld, nr, nq, ss, N, P->gpart, P->gram_d, s));
+      }
+      CK(hipStreamSynchronize(s));
+      const double* G = P->gram_h;
+      for (int i = 0; i < nr * 16; ++i)
+        if (!std::isfinite(G[i])) return finish_ev(st, events, RSFDE_ENONFINITE, total, cycles, beta, bnorm);
+      int kp = block_factor(G, nq, ss, C, R);
+      if (P->trace) {
+        std::fprintf(stderr, "[rsfde s-step] cycle %d m %d ss %d pivots %d  diag(U^T U)", cycles, m,
+                     ss, kp);
+        for (int k = 0; k < ss; ++k) std::fprintf(stderr, " %.3e", G[(nq + k) * 16 + k]);
+        std::fprintf(stderr, "  R_kk");
+        for (int k = 0; k < kp; ++k) std::fprintf(stderr, " %.3e", R[(size_t)k * ss + k]);
+        std::fprintf(stderr, "\n");
+      }
+      std::vector<double> Capply;  // projections still to subtract from the stored block
+      bool second = false;
+      if (kp < ss) {
+        // second block pass: U <- U - Q C, then project and factor again
+        ++events;
+        std::vector<double> coef((size_t)nq * ss + (size_t)ss * ss, 0.0);
+        std::copy(C.begin(), C.end(), coef.begin());
+        for (int k = 0; k < ss; ++k) coef[(size_t)nq * ss + k * ss + k] = 1.0;
+        std::copy(coef.begin(), coef.end(), P->coef_h);
+        CK(hipMemcpyAsync(P->coef_d, P->coef_h, coef.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+        {
+          ProfScope ps(P, s, kCatBupd, 8.0 * (double)(nq + 2 * ss) * (double)N);
+          CK(launch_bupd(P->V, ld, nq, nq, ss, N, P->coef_d, s));
+        }
+        {
+          ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)N);
+          CK(launch_bgram(P->V, ld, nr, nq, ss, N, P->gpart, P->gram_d, s));
+        }
+        CK(hipStreamSynchronize(s));
+        kp = block_factor(P->gram_h, nq, ss, C2, R2);
+        if (P->trace) {
+          std::fprintf(stderr, "[rsfde s-step]   second pass pivots %d  diag(U'^T U')", kp);
+          for (int k = 0; k < ss; ++k) std::fprintf(stderr, " %.3e", P->gram_h[(nq + k) * 16 + k]);
+          std::fprintf(stderr, "\n");
+        }
+        if (kp == 0 && m > 0) {
+          // even the first direction of the block is numerically in the span of
+          // the basis (which has lost orthogonality): end the cycle with the m
+          // columns built so far and restart from the true residual
+          ++events;
+          jc = m;
+          break;
+        }
+        if (kp == 0) {
+          // at the start of a cycle: finish this solve with the one-vector form
+          rsfde_solver_opts o1 = *o;
+          o1.sstep = 0;
+          o1.max_iters = std::max(1, o->max_iters - total);
+          const int rc1 = solve_core(P, x, &o1, st, s);
+          if (st) {
+            st->iters += total;
+            st->reserved = events + 1;
+          }
+          return rc1;
+        }
+        for (size_t i = 0; i < C.size(); ++i) C[i] += C2[i];  // total projections
+        R = R2;
+        second = true;
+      }
+      Capply = second ? C2 : C;
+      if (kp < ss) {  // keep the leading kp directions of the block
+        ++events;
+        C = lead_cols(C, nq, ss, kp);
+        Capply = lead_cols(Capply, nq, ss, kp);
+        R = lead_square(R, ss, kp);
+        ss = kp;
+        nr = nq + ss;
+      }
+      // Hessenberg columns m..m+ss-1:  H_blk = (S_r - H_old Top) T^{-1}
+      {
+        std::vector<double> Sl((size_t)nr * ss, 0.0), Sr((size_t)nr * ss, 0.0);
+        // S column 0 = e_m; column k>=1: rows < nq = C[:, k-1], rows nq.. = R[:, k-1]
+        auto Scol = [&](int row, int k) -> double {
+          if (k == 0) return row == m ? 1.0 : 0.0;
+          if (row < nq) return C[(size_t)row * ss + (k - 1)];
+          return R[(size_t)(row - nq) * ss + (k - 1)];
+        };
+        for (int r = 0; r < nr; ++r)
+          for (int k = 0; k < ss; ++k) {
+            Sl[(size_t)r * ss + k] = Scol(r, k);
+            Sr[(size_t)r * ss + k] = Scol(r, k + 1) + theta * Scol(r, k);
+          }
+        // T = rows m..m+ss-1 of S_l (upper triangular), Top = rows < m
+        std::vector<double> T((size_t)ss * ss);
+        for (int a = 0; a < ss; ++a)
+          for (int k = 0; k < ss; ++k) T[(size_t)a * ss + k] = Sl[(size_t)(m + a) * ss + k];
+        const std::vector<double> Ti = upper_inverse(T, ss);
+        std::vector<double> X((size_t)nr * ss);
+        for (int r = 0; r < nr; ++r)
+          for (int k = 0; k < ss; ++k) {
+            double v = Sr[(size_t)r * ss + k];
+            for (int c = 0; c < m; ++c) v -= Hraw[(size_t)r * RS + c] * Sl[(size_t)c * ss + k];
+            X[(size_t)r * ss + k] = v;
+          }
+        for (int r = 0; r < nr; ++r)
+          for (int k = 0; k < ss; ++k) {
+            double v = 0.0;
+            for (int a = 0; a <= k; ++a) v += X[(size_t)r * ss + a] * Ti[(size_t)a * ss + k];
+            // Hessenberg: entries below the subdiagonal are rounding noise
+            Hraw[(size_t)r * RS + (m + k)] = (r <= m + k + 1) ? v : 0.0;
+          }
+      }
+      // direction map W for q_{m+1..m+ss-1} (q_{m+ss} is the next block's first direction)
+      for (int k = 0; k + 1 < ss; ++k) {
+        const int col = m + 1 + k;
+        for (int i = 0; i <= col; ++i) {
+          double v = (i == col) ? 1.0 : 0.0;
+          for (int c = 0; c < nq; ++c) v -= W[(size_t)i * RS + c] * C[(size_t)c * ss + k];
+          for (int l = 0; l < k; ++l) v -= W[(size_t)i * RS + (m + 1 + l)] * R[(size_t)l * ss + k];
+          W[(size_t)i * RS + col] = v / R[(size_t)k * ss + k];
+        }
+      }
+      // Givens rotations and residual estimates, column by column
+      for (int k = 0; k < ss && jc < 0; ++k) {
+        const int c = m + k;
+        for (int r = 0; r <= c + 1; ++r) Hrot[(size_t)r * RS + c] = Hraw[(size_t)r * RS + c];
+        for (int i = 0; i < c; ++i) {
+          const double a = Hrot[(size_t)i * RS + c], b2 = Hrot[(size_t)(i + 1) * RS + c];
+          Hrot[(size_t)i * RS + c] = cs[i] * a + sn[i] * b2;
+          Hrot[(size_t)(i + 1) * RS + c] = -sn[i] * a + cs[i] * b2;
+        }
+        const double a = Hrot[(size_t)c * RS + c], b2 = Hrot[(size_t)(c + 1) * RS + c];
+        const double den = std::hypot(a, b2);
+        cs[c] = den > 0.0 ? a / den : 1.0;
+        sn[c] = den > 0.0 ? b2 / den : 0.0;
+        Hrot[(size_t)c * RS + c] = den;
+        Hrot[(size_t)(c + 1) * RS + c] = 0.0;
+        g[c + 1] = -sn[c] * g[c];
+        g[c] = cs[c] * g[c];
+        if (!std::isfinite(den) || !std::isfinite(g[c + 1]))
+          return finish_ev(st, events, RSFDE_ENONFINITE, total + c, cycles, beta, bnorm);
+        if (std::fabs(g[c + 1]) <= thresh) jc = c + 1;
+      }
+      if (jc > 0) break;
+      if (m + ss < jmax) {  // the block becomes orthonormal basis vectors
+        const size_t nc = (size_t)nq * ss + (size_t)ss * ss;
+        const std::vector<double> Ri = upper_inverse(R, ss);
+        std::copy(Capply.begin(), Capply.end(), P->coef_h);
+        std::copy(Ri.begin(), Ri.end(), P->coef_h + (size_t)nq * ss);
+        CK(hipMemcpyAsync(P->coef_d, P->coef_h, nc * sizeof(double), hipMemcpyHostToDevice, s));
+        ProfScope ps(P, s, kCatBupd, 8.0 * (double)(nq + 2 * ss) * (double)N);
+        CK(launch_bupd(P->V, ld, nq, nq, ss, N, P->coef_d, s));
+      }
+      m += ss;
+    }
+    if (jc < 0) jc = m;
+    // y = R^{-1} g (rotated Hessenberg), coefficients of the stored P^{-1} u: W y
+    std::vector<double> y(jc);
+    for (int i = jc - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int k = i + 1; k < jc; ++k) v -= Hrot[(size_t)i * RS + k] * y[k];
+      const double d = Hrot[(size_t)i * RS + i];
+      y[i] = d != 0.0 ? v / d : 0.0;
+    }
+    CK(hipStreamSynchronize(s));  // the staging buffer may still feed an update copy
+    for (int i = 0; i < jc; ++i) {
+      double v = 0.0;
+      for (int l = i; l < jc; ++l) v += W[(size_t)i * RS + l] * y[l];
+      P->coef_h[i] = v;
+    }
+    CK(hipMemcpyAsync(P->coef_d, P->coef_h, (size_t)jc * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+      ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
+      CK(launch_update_coef(P->Z, ld, jc, x, N, P->coef_d, s));
+    }
+    total += jc;
+  }
+}
+
 }  // namespace
 }  // namespace rsfde
 
@@ -689,6 +1039,10 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   P->dt = dt;
   P->dpen = dt / eta;
   P->max_restart = max_restart;
+  {
+    const char* tr = std::getenv("RSFDE_TRACE");
+    P->trace = tr && tr[0] == '1';
+  }
 
   // Section 2: mesh widths and unit-k coefficients c = dt c_alpha / h^alpha.
   const double hx = (grid->x_hi - grid->x_lo) / (n1 + 1);
@@ -733,12 +1087,20 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   P->P2 = q;
   AL(P->ks, 1);
   AL(P->rw.partial, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
+  AL(P->gpart, (size_t)16 * 16 * kGramMaxTiles * kGramBlocks);
+  AL(P->coef_d, (size_t)16 * 16 * kGramMaxTiles + 256);
 #undef AL
   if (hipHostMalloc((void**)&P->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
       hipSuccess)
     return fail(RSFDE_ENOMEM);
   std::memset((void*)P->hs, 0, sizeof(HostStatus));
   if (hipHostGetDevicePointer((void**)&P->hs_dev, P->hs, 0) != hipSuccess) return fail(RSFDE_EHIP);
+  if (hipHostMalloc((void**)&P->gram_h, sizeof(double) * 16 * 16 * kGramMaxTiles,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void**)&P->coef_h, sizeof(double) * (16 * 16 * kGramMaxTiles + 256),
+                    hipHostMallocDefault) != hipSuccess)
+    return fail(RSFDE_ENOMEM);
+  if (hipHostGetDevicePointer((void**)&P->gram_d, P->gram_h, 0) != hipSuccess) return fail(RSFDE_EHIP);
   for (auto& e : P->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RSFDE_EHIP);
 

@@ -42,6 +42,12 @@ FAMILIES = [
     (r"k_residual\b", "residual"),
     (r"k_rhs\b", "rhs"),
     (r"k_dot\b", "dot"),
+    (r"k_bgram<", "block_gram"),
+    (r"k_bupd<", "block_update"),
+    (r"k_cd_rows_fwd<", "cd_rows_fwd"),
+    (r"k_cd_cols<", "cd_cols"),
+    (r"k_cd_rows_inv<", "cd_rows_inv"),
+    (r"k_scale_copy", "other"),
 ]
 
 # One-block finishing kernels launched right after a streaming kernel belong
@@ -53,6 +59,7 @@ FINISHERS = [
     (r"k_residual_finish", "residual"),
     (r"k_rhs_finish", "rhs"),
     (r"k_dot_finish", "dot"),
+    (r"k_bgram_finish", "block_gram"),
 ]
 
 
@@ -71,7 +78,7 @@ def family(name: str) -> str:
         if re.search(pat, name):
             suffix = ""
             m = re.search(r"<(double|float)", name)
-            if m and fam.startswith("pc_"):
+            if m and (fam.startswith("pc_") or fam.startswith("cd_")):
                 suffix = "<" + m.group(1) + ">"
             return fam + suffix
     return "other"
