@@ -192,6 +192,26 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
                        double* lam_prev, double* mu_guess, double* dk_dev, rsfde_stats* stats,
                        void* stream);
 
+/* Advance an ensemble of independent plans (finite-difference directions,
+ * parameter sweeps, several initial fields; SURVEY's batched solves) by m
+ * implicit steps each (rsfde_step semantics: initial guess 2u^{k-1} - u^{k-2},
+ * f_kind, opts), concurrently: one host thread per plan, each enqueueing on
+ * streams[i] (or that plan's set-up stream when streams is NULL).  Members
+ * overlap on the GPU when their streams differ, which keeps small grids from
+ * leaving most compute units idle.
+ *   plans  : count distinct plans (on the same device)
+ *   u0     : count device vectors [n2][n1] of the matching plan (read only)
+ *   u_out  : count device vectors receiving u^m (may alias neither u0 nor work)
+ *   work   : 2*count device vectors (scratch for the time levels)
+ *   stats  : NULL or count entries: iterations summed over the member's steps,
+ *            status of its last step
+ * Returns RSFDE_OK or the first member's error (every member runs to its end
+ * or first error).  Errors: EINVAL, ENOTCONV, ENONFINITE, EHIP. */
+int rsfde_march_ensemble(int32_t count, const rsfde_plan* plans, const double* const* u0,
+                         int32_t m, int32_t f_kind, const rsfde_solver_opts* opts,
+                         double* const* u_out, double* const* work, rsfde_stats* stats,
+                         void* const* streams);
+
 /* Kernel timing (measurement support, not part of the method).
  * rsfde_profile(plan, 1) starts bracketing every kernel the plan launches with
  * a pair of HIP events on the launch stream, tagged with the kernel family and

@@ -77,6 +77,10 @@ def _load():
     lib.rsfde_solve.argtypes = [P, P, P, C.POINTER(rsfde_solver_opts), C.POINTER(rsfde_stats), P]
     lib.rsfde_adjoint_step.argtypes = [P, P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P, P,
                                        P, C.POINTER(rsfde_stats), P]
+    PP = C.POINTER(C.c_void_p)
+    lib.rsfde_march_ensemble.argtypes = [C.c_int32, PP, PP, C.c_int32, C.c_int32,
+                                         C.POINTER(rsfde_solver_opts), PP, PP,
+                                         C.POINTER(rsfde_stats), PP]
     lib.rsfde_profile.argtypes = [P, C.c_int32]
     lib.rsfde_profile_read.argtypes = [P, C.POINTER(rsfde_kernel_profile), C.c_int32,
                                        C.POINTER(C.c_int32)]
@@ -84,7 +88,7 @@ def _load():
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
     for f in ("rsfde_setup", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
-              "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_adjoint_step", "rsfde_destroy",
+              "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_march_ensemble", "rsfde_adjoint_step", "rsfde_destroy",
               "rsfde_profile", "rsfde_profile_read"):
         getattr(lib, f).restype = C.c_int
     return lib
@@ -208,6 +212,22 @@ def rsfde_adjoint_step(plan, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev, mu_
     if check:
         _raise(rc, "rsfde_adjoint_step")
     return st
+
+
+def rsfde_march_ensemble(plans, u0s, m, f_kind, opts, u_outs, works, streams=None, check=True):
+    """plans: list of plan handles; u0s, u_outs: tensors (one per plan); works:
+    2 tensors per plan; streams: None or one torch stream (or raw handle) per plan."""
+    n = len(plans)
+    arr = lambda xs: (C.c_void_p * len(xs))(*[_ptr(x) if not isinstance(x, C.c_void_p) else x.value  # noqa: E731
+                                              for x in xs])
+    hp = (C.c_void_p * n)(*[p.value if isinstance(p, C.c_void_p) else p for p in plans])
+    st = (rsfde_stats * n)()
+    sp = None if streams is None else (C.c_void_p * n)(*[_stream(s) for s in streams])
+    rc = _lib.rsfde_march_ensemble(n, hp, arr(u0s), int(m), int(f_kind), C.byref(opts),
+                                   arr(u_outs), arr(works), st, sp)
+    if check:
+        _raise(rc, "rsfde_march_ensemble")
+    return [st[i] for i in range(n)]
 
 
 def rsfde_destroy(plan):

@@ -29,36 +29,40 @@ struct LdsLayout {
   static constexpr bool linear = check();
 };
 
-template <typename T, class F, int t>
+// ST: LDS stride between consecutive slots of one FFT.  A block that runs BC
+// FFTs with the FFT index fastest in the thread layout (the column kernels)
+// interleaves their regions (slot * BC + b): the lanes of a wavefront then
+// touch consecutive words, free of bank conflicts.
+template <typename T, class F, int t, int ST>
 __device__ __forceinline__ void lds_put(const cpx<T>* reg, int tau, T* lds, bool im) {
   using LL = LdsLayout<F, t>;
   if constexpr (LL::linear) {
-    T* b = lds + lds_pad(F::pos(t, tau, 0));
+    T* b = lds + lds_pad(F::pos(t, tau, 0)) * ST;
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      b[LL::delta(e)] = im ? reg[e].im : reg[e].re;
+      b[LL::delta(e) * ST] = im ? reg[e].im : reg[e].re;
     });
   } else {
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      lds[lds_pad(F::pos(t, tau, e))] = im ? reg[e].im : reg[e].re;
+      lds[lds_pad(F::pos(t, tau, e)) * ST] = im ? reg[e].im : reg[e].re;
     });
   }
 }
 
-template <typename T, class F, int t>
+template <typename T, class F, int t, int ST>
 __device__ __forceinline__ void lds_get(cpx<T>* reg, int tau, const T* lds, bool im) {
   using LL = LdsLayout<F, t>;
   if constexpr (LL::linear) {
-    const T* b = lds + lds_pad(F::pos(t, tau, 0));
+    const T* b = lds + lds_pad(F::pos(t, tau, 0)) * ST;
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      (im ? reg[e].im : reg[e].re) = b[LL::delta(e)];
+      (im ? reg[e].im : reg[e].re) = b[LL::delta(e) * ST];
     });
   } else {
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
-      (im ? reg[e].im : reg[e].re) = lds[lds_pad(F::pos(t, tau, e))];
+      (im ? reg[e].im : reg[e].re) = lds[lds_pad(F::pos(t, tau, e)) * ST];
     });
   }
 }
@@ -66,15 +70,15 @@ __device__ __forceinline__ void lds_get(cpx<T>* reg, int tau, const T* lds, bool
 // Exchange registers between stage layouts through this FFT's LDS region.
 // Real and imaginary parts go through the same region one after the other so
 // that the region holds only L scalars.
-template <typename T, class F, int TF, int TT>
+template <typename T, class F, int TF, int TT, int ST = 1>
 __device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds) {
-  lds_put<T, F, TF>(reg, tau, lds, false);
+  lds_put<T, F, TF, ST>(reg, tau, lds, false);
   __syncthreads();
-  lds_get<T, F, TT>(reg, tau, lds, false);
+  lds_get<T, F, TT, ST>(reg, tau, lds, false);
   __syncthreads();
-  lds_put<T, F, TF>(reg, tau, lds, true);
+  lds_put<T, F, TF, ST>(reg, tau, lds, true);
   __syncthreads();
-  lds_get<T, F, TT>(reg, tau, lds, true);
+  lds_get<T, F, TT, ST>(reg, tau, lds, true);
   __syncthreads();
 }
 
@@ -90,25 +94,25 @@ __device__ __forceinline__ void materialize(cpx<T>* r) {
 
 // Forward DIF sweep: natural order (stage-0 positions) in, digit-reversed
 // spectrum (last-stage positions) out.
-template <typename T, class F, bool MAT = true>
+template <typename T, class F, bool MAT = true, int ST = 1>
 __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = decltype(tt)::value;
     F::template dif_stage<T, t>(reg, tau, tw);
-    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1>(reg, tau, lds);
+    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST>(reg, tau, lds);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }
 
 // Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order out.
-template <typename T, class F, bool MAT = true>
+template <typename T, class F, bool MAT = true, int ST = 1>
 __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = F::NS - 1 - decltype(tt)::value;
     F::template dit_stage<T, t>(reg, tau, tw);
-    if constexpr (t > 0) lds_exchange<T, F, t, t - 1>(reg, tau, lds);
+    if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST>(reg, tau, lds);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }

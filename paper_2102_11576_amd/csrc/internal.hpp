@@ -136,7 +136,7 @@ hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, si
 // s-step blocks (krylov_block.hip).  G (pinned, device-visible, [nr][16]) =
 // [V_0 .. V_{nr-1}]^T [V_{m1} .. V_{m1+s-1}]; gpart holds
 // 16 * 16 * kGramMaxTiles * kGramBlocks partial sums.
-constexpr int kGramBlocks = 512;
+constexpr int kGramBlocks = 1024;
 constexpr int kGramMaxTiles = 5;  // up to 80 Gram rows
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, hipStream_t st);

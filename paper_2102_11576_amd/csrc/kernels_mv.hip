@@ -106,15 +106,15 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
     reg[e].re = (va && in) ? z[(size_t)p * n1 + ca] : 0.0;
     reg[e].im = (vb && in) ? z[(size_t)p * n1 + cb] : 0.0;
   });
-  double* my = lds + b * lds_len(L);
-  fft_forward<double, F>(reg, tau, tw, my);
+  double* my = lds + b;  // regions interleaved (stride BC)
+  fft_forward<double, F, true, C::BC>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const double s = sym[F::pos(F::NS - 1, tau, e)] * coef;
     reg[e].re *= s;
     reg[e].im *= s;
   });
-  fft_inverse<double, F>(reg, tau, tw, my);
+  fft_inverse<double, F, true, C::BC>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);

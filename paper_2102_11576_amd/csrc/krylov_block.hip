@@ -47,7 +47,29 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 
   const size_t nchunks = N / 8;  // 8 elements per wave step
   const size_t gw = (size_t)gridDim.x * 4;
-  for (size_t ch = (size_t)blockIdx.x * 4 + wid; ch < nchunks; ch += gw) {
+  size_t ch = (size_t)blockIdx.x * 4 + wid;
+  // four chunks per iteration: all loads issued before the products, so each
+  // wave keeps 4 (NT + 1) 16-byte loads per lane in flight
+  constexpr int UR = 4;
+  for (; ch + (UR - 1) * gw < nchunks; ch += UR * gw) {
+    double2 b[UR], a[UR][NT];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const size_t e = (ch + u * gw) * 8 + 2 * k4;
+      b[u] = bvalid ? *reinterpret_cast<const double2*>(brow + e) : double2{0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        a[u][t] = avalid[t] ? *reinterpret_cast<const double2*>(arow[t] + e) : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t].x, b[u].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t].y, b[u].y, acc[t], 0, 0, 0);
+      }
+  }
+  for (; ch < nchunks; ch += gw) {
     const size_t e = ch * 8 + 2 * k4;
     const double2 b = bvalid ? *reinterpret_cast<const double2*>(brow + e) : double2{0.0, 0.0};
     double2 a[NT];
@@ -186,7 +208,7 @@ __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, si
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, hipStream_t st) {
   if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
-  int nb = (int)((N / 8 + 4 * 16 - 1) / (4 * 16));  // >= 16 wave steps per wave
+  int nb = (int)((N / 8 + 4 * 16 - 1) / (4 * 16));  // >= 16 chunks per wave
   if (nb < 1) nb = 1;
   if (nb > kGramBlocks) nb = kGramBlocks;
   const int nt = (nr + 15) / 16;

@@ -39,7 +39,7 @@ struct CdCfg {
 
 // In: reg[e].re = x at sequence position pos(0, tau, e) (zero at positions >= n).
 // Out: reg[e].re = (S x) at the same position (unspecified at positions >= n).
-template <typename T, class F>
+template <typename T, class F, int ST = 1>
 __device__ __forceinline__ void chirp_dst(cpx<T>* reg, int tau, const cpx<T>* __restrict__ chn,
                                           const cpx<T>* __restrict__ khat,
                                           const cpx<T>* __restrict__ tw, T* lds, int n) {
@@ -51,12 +51,12 @@ __device__ __forceinline__ void chirp_dst(cpx<T>* reg, int tau, const cpx<T>* __
     reg[e].re = x * c.re;
     reg[e].im = x * c.im;
   });
-  fft_forward<T, F>(reg, tau, tw, lds);
+  fft_forward<T, F, true, ST>(reg, tau, tw, lds);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     reg[e] = cmul(reg[e], khat[F::pos(F::NS - 1, tau, e)]);
   });
-  fft_inverse<T, F>(reg, tau, tw, lds);
+  fft_inverse<T, F, true, ST>(reg, tau, tw, lds);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(CdCfg<L>::THR_C) void k_cd_cols(
   const int b = threadIdx.x % C::BC, tau = threadIdx.x / C::BC;
   const int c = xcd_remap(blockIdx.x, gridDim.x) * C::BC + b;
   const bool vc = c < n1;
-  T* my = lds + b * lds_len(L);
+  T* my = lds + b;  // regions interleaved (stride BC)
   cpx<T> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(CdCfg<L>::THR_C) void k_cd_cols(
     reg[e].re = (vc && p < n2) ? in[(size_t)p * n1 + c] : T(0);
     reg[e].im = T(0);
   });
-  chirp_dst<T, F>(reg, tau, chn, khat, tw, my, n2);
+  chirp_dst<T, F, C::BC>(reg, tau, chn, khat, tw, my, n2);
   const double ax = 1.0 - kx * (vc ? lamx[c] : 0.0);
   T w[F::PP];
   static_for<F::PP>([&](auto ee) {
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(CdCfg<L>::THR_C) void k_cd_cols(
     w[e] = p < n2 ? reg[e].re : T(0);
     reg[e].re = w[e] / e1;
   });
-  chirp_dst<T, F>(reg, tau, chn, khat, tw, my, n2);
+  chirp_dst<T, F, C::BC>(reg, tau, chn, khat, tw, my, n2);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(CdCfg<L>::THR_C) void k_cd_cols(
     const T e2 = (T)(ax + dpen - ky * (p < n2 ? lamy[p] : 0.0));
     reg[e].re = w[e] / e2;
   });
-  chirp_dst<T, F>(reg, tau, chn, khat, tw, my, n2);
+  chirp_dst<T, F, C::BC>(reg, tau, chn, khat, tw, my, n2);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);

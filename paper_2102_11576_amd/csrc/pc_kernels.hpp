@@ -120,9 +120,9 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].re = ok ? sgn * Q[(size_t)row * ld + ca] : (T)0;
     reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
   });
-  T* my = lds + b * lds_len(L);
+  T* my = lds + b;  // regions interleaved (stride BC)
   // (no register materialisation between the sweeps here: it measured slower)
-  fft_forward<T, F, false>(reg, tau, tw, my);
+  fft_forward<T, F, false, C::BC>(reg, tau, tw, my);
   // spectrum = 2 rho_b - 2i rho_a; keep rho_b for the second column
   const T lxa = valid ? kx * lamx_slot[ca] : (T)0;
   const T lxb = valid ? kx * lamx_slot[cb] : (T)0;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].re = r * e1;
     reg[e].im = -r * e2;
   });
-  fft_inverse<T, F, false>(reg, tau, tw, my);
+  fft_inverse<T, F, false, C::BC>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     reg[e].re = r * e1;
     reg[e].im = -r * e2;
   });
-  fft_inverse<T, F, false>(reg, tau, tw2, my);
+  fft_inverse<T, F, false, C::BC>(reg, tau, tw2, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);

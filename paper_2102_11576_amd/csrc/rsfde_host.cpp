@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <map>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/rsfde.h"
@@ -1299,6 +1300,85 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
       launch_adj_lambda(mu, u_prev, P->mask, P->dt, f_kind, lam_prev, P->N, s) != hipSuccess)
     return finish(stats, RSFDE_EHIP, stats ? stats->iters : 0, 0, 0, 0);
   if (hipStreamSynchronize(s) != hipSuccess) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
+  return RSFDE_OK;
+}
+
+int rsfde_march_ensemble(int32_t count, const rsfde_plan* plans, const double* const* u0,
+                         int32_t m, int32_t f_kind, const rsfde_solver_opts* opts,
+                         double* const* u_out, double* const* work, rsfde_stats* stats,
+                         void* const* streams) {
+  if (count < 1 || !plans || !u0 || !u_out || !work || !opts || m < 0) return RSFDE_EINVAL;
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return RSFDE_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !u0[i] || !u_out[i] || !work[2 * i] || !work[2 * i + 1]) return RSFDE_EINVAL;
+    const double* bufs[4] = {u0[i], u_out[i], work[2 * i], work[2 * i + 1]};
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (bufs[a] == bufs[b]) return RSFDE_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return RSFDE_EINVAL;
+    const int rc = rsfde::validate_opts(&plans[i]->p, opts);
+    if (rc) return rc;
+  }
+  std::vector<int> rcs(count, RSFDE_OK);
+  auto member = [&](int i) {
+    Plan* P = &plans[i]->p;
+    void* st = streams ? streams[i] : nullptr;
+    double* slot[3] = {u_out[i], work[2 * i], work[2 * i + 1]};
+    const double* prev2 = nullptr;
+    const double* prev = u0[i];
+    int64_t iters = 0;
+    rsfde_stats s1{};
+    int last = -1;  // slot index of prev
+    for (int k = 1; k <= m; ++k) {
+      // a slot that holds neither u^{k-1} nor u^{k-2}; the last step writes u_out
+      int nx = 0;
+      if (k == m) {
+        nx = 0;
+      } else {
+        for (nx = 0; nx < 3; ++nx)
+          if (slot[nx] != prev && slot[nx] != prev2) break;
+      }
+      if (slot[nx] == prev || slot[nx] == prev2) {  // u_out busy: use a free work slot
+        for (nx = 1; nx < 3; ++nx)
+          if (slot[nx] != prev && slot[nx] != prev2) break;
+      }
+      const int rc = rsfde_step(plans[i], prev, prev2, f_kind, opts, slot[nx], &s1, st);
+      iters += s1.iters;
+      if (rc != RSFDE_OK) {
+        rcs[i] = rc;
+        break;
+      }
+      prev2 = prev;
+      prev = slot[nx];
+      last = nx;
+    }
+    if (rcs[i] == RSFDE_OK) {
+      rsfde::DeviceGuard g(P->dev);
+      hipStream_t s = rsfde::pick(P, st);
+      if (m == 0) {
+        if (hipMemcpyAsync(u_out[i], u0[i], P->N * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+          rcs[i] = RSFDE_EHIP;
+      } else if (last != 0) {
+        if (hipMemcpyAsync(u_out[i], slot[last], P->N * sizeof(double), hipMemcpyDeviceToDevice,
+                           s) != hipSuccess)
+          rcs[i] = RSFDE_EHIP;
+      }
+      if (rcs[i] == RSFDE_OK && hipStreamSynchronize(s) != hipSuccess) rcs[i] = RSFDE_EHIP;
+    }
+    if (stats) {
+      stats[i] = s1;
+      stats[i].iters = (int32_t)std::min<int64_t>(iters, INT32_MAX);
+      stats[i].status = rcs[i];
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(count);
+  for (int i = 0; i < count; ++i) th.emplace_back(member, i);
+  for (auto& t : th) t.join();
+  for (int i = 0; i < count; ++i)
+    if (rcs[i] != RSFDE_OK) return rcs[i];
   return RSFDE_OK;
 }
 

@@ -172,6 +172,27 @@ def counters(fetch_csv: str, write_csv: str, n1: int, n2: int, copy_bytes: float
     return out
 
 
+def sq_summary(csv_paths) -> str:
+    """Per-family sums of SQ counters (one or more --pmc runs), divided by the
+    launch count: instruction mix, VALU and LDS activity and LDS bank
+    conflicts of each kernel family."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            f = family(r["Kernel_Name"])
+            if finisher_parent(r["Kernel_Name"]):
+                continue
+            vals[f][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[f].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+    names = sorted({c for f in vals for c in vals[f]})
+    lines = ["family           " + " ".join(f"{n[3:]:>20s}" for n in names) + "  (per launch)"]
+    for f in sorted(vals, key=lambda k: -vals[k].get("SQ_BUSY_CYCLES", 0.0)):
+        n = max(1, len(disp[f]))
+        lines.append(f"{f:16s} " + " ".join(f"{vals[f].get(c, 0.0) / n:20.4g}" for c in names))
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -184,7 +205,12 @@ def main(argv=None):
     b.add_argument("--n2", type=int, required=True)
     b.add_argument("--copy-bytes", type=float, default=256.0 * 1024 * 1024)
     b.add_argument("--out", required=True)
+    c = sub.add_parser("sq")
+    c.add_argument("csv", nargs="+")
     args = ap.parse_args(argv)
+    if args.cmd == "sq":
+        print(sq_summary(args.csv))
+        return 0
     if args.cmd == "stats":
         print(stats(args.csv))
     else:

@@ -146,3 +146,20 @@ class RsfdePlan:
             if keep and k in keep:
                 saved[k] = bufs[cur].clone()
         return bufs[cur], iters, saved
+
+
+def march_ensemble(plans, u0s, m, f_kind, opts, streams=None):
+    """Advance independent plans (an ensemble: FD directions, parameter sweeps)
+    by m steps each, concurrently (rsfde_march_ensemble: one host thread and,
+    with `streams`, one stream per member).  Returns (list of u^m, list of
+    StepStats with the iterations summed over the member's steps)."""
+    if len(plans) != len(u0s):
+        raise ValueError("one initial field per plan")
+    outs, works = [], []
+    for pl, u in zip(plans, u0s):
+        L._check_vec(u, pl.N, "u0")
+        outs.append(pl.empty())
+        works += [pl.empty(), pl.empty()]
+    sts = L.rsfde_march_ensemble([pl.handle for pl in plans], u0s, m, f_kind, opts, outs, works,
+                                 streams)
+    return outs, [StepStats(s.iters, s.restarts, s.relres, s.status) for s in sts]
