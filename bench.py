@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--mode", choices=["march", "kernels"], default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-vector", action="store_true",
                     help="skip the one-vector-per-step comparison march (profiling runs)")
     ap.add_argument("--sstep", type=int, default=8,
@@ -212,6 +213,44 @@ def adjoint_rate(log, sstep=0):
             errs.append(abs(fd - an) / abs(an))
         res["fd_rel_err_2_dirs"] = errs
     return res
+
+
+def ensemble_rate(log, sstep=0, members=8, steps=8):
+    """Independent marches (FD directions / parameter sweeps) at 511^2 (c4 grid):
+    `members` plans advanced `steps` steps each, concurrently on their own
+    streams (rsfde_march_ensemble) against the same members one after another."""
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts, march_ensemble
+    from workloads.configs import make_config, fd_direction
+    w = make_config("c4")
+    dev = torch.device("cuda:0")
+    opts = make_opts(w.restart, 100000, w.tol, sstep=sstep)
+    plans, u0s = [], []
+    for i in range(members):
+        plans.append(RsfdePlan.from_workload(w, kx=1.0 + 0.02 * i, device=dev))
+        du, _, _ = fd_direction(w.u0.shape, i)
+        u0s.append(torch.as_tensor(w.u0 + 1e-3 * du * w.mask, device=dev).reshape(-1).contiguous())
+    streams = [torch.cuda.Stream() for _ in plans]
+    march_ensemble(plans, u0s, 1, w.f_kind, opts, streams)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, _ = march_ensemble(plans, u0s, steps, w.f_kind, opts, streams)
+    torch.cuda.synchronize()
+    t_conc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for pl, u0 in zip(plans, u0s):
+        pl.march(u0, steps, w.f_kind, opts)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for pl in plans:
+        pl.close()
+    unk = float(w.N) * steps * members
+    log(f"ensemble: {members} x {steps} steps at 511^2: {t_conc:.3f}s concurrent, {t_seq:.3f}s sequential")
+    return {"workload": f"{members} independent marches of {steps} steps on the 511x511 c4 grid "
+                        f"(perturbed u0, kx = 1 + 0.02 i)",
+            "concurrent_unknown_timesteps_per_s": unk / t_conc,
+            "sequential_unknown_timesteps_per_s": unk / t_seq,
+            "speedup": t_seq / t_conc}
 
 
 def traffic_for(kernel, bytes_per_launch):
@@ -382,6 +421,9 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint"] = adjoint_rate(log, args.sstep)
+
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_rate(log, args.sstep)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
