@@ -49,6 +49,8 @@ def fft_flops(family, n1, n2):
         "pc_rows_fwd": ((n2 + 1) // 2) * f(Ldx),         # forward per row pair
         "pc_cols": ((n1 + 1) // 2) * 3 * f(Ldy),         # forward + two inverses per column pair
         "pc_rows_inv": n2 * f(Ldx),                      # inverse per row
+        # pass C (inverse per row) fused with the matvec row pass (conv per row pair)
+        "pc_inv_mv_rows": n2 * f(Ldx) + ((n2 + 1) // 2) * 2 * f(Lcx),
     }
     return table.get(family)
 METRIC = "unknown·timesteps/s at 2047², mixed vs FP64 at 1e-8 rel err; adjoint grads/s"

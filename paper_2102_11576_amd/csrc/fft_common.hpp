@@ -67,19 +67,53 @@ __device__ __forceinline__ void lds_get(cpx<T>* reg, int tau, const T* lds, bool
   }
 }
 
+// Thread that holds sequence position p in the layout of stage t (inverse of
+// F::pos: p = (beta / s) bl + beta % s + m s, beta = tau + u TPF).
+template <class F>
+constexpr int owner_of(int t, int p) {
+  const int s = F::stride(t), bl = F::blocklen(t);
+  const int beta = (p / bl) * s + (p % s);
+  return beta % F::TPF;
+}
+
+// True when the exchange from layout TF to layout TT only moves data among
+// the threads of one wavefront: every position's owners in both layouts fall
+// in the same group of TW consecutive threads (TW = threads of one FFT in a
+// wavefront: 64, or 64 / BC with BC FFTs interleaved per wavefront).
+template <class F, int TF, int TT, int TW>
+constexpr bool exchange_in_wave() {
+  if (F::TPF < TW || TW < 1) return false;
+  for (int p = 0; p < F::TPF * F::PP; ++p)
+    if (owner_of<F>(TF, p) / TW != owner_of<F>(TT, p) / TW) return false;
+  return true;
+}
+
 // Exchange registers between stage layouts through this FFT's LDS region.
 // Real and imaginary parts go through the same region one after the other so
-// that the region holds only L scalars.
-template <typename T, class F, int TF, int TT, int ST = 1>
+// that the region holds only L scalars.  When the exchange stays inside each
+// wavefront (TW > 0 and exchange_in_wave), no block barrier is needed: a
+// wavefront's LDS operations complete in order, and every wavefront only
+// rewrites the positions it reads (the fences keep the compiler from
+// reordering the LDS accesses).
+template <typename T, class F, int TF, int TT, int ST = 1, int TW = 0>
 __device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds) {
+  constexpr bool wave_local = TW > 0 && exchange_in_wave<F, TF, TT, TW>();
+  auto sync = [] {
+    if constexpr (wave_local) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      __syncthreads();
+    }
+  };
   lds_put<T, F, TF, ST>(reg, tau, lds, false);
-  __syncthreads();
+  sync();
   lds_get<T, F, TT, ST>(reg, tau, lds, false);
-  __syncthreads();
+  sync();
   lds_put<T, F, TF, ST>(reg, tau, lds, true);
-  __syncthreads();
+  sync();
   lds_get<T, F, TT, ST>(reg, tau, lds, true);
-  __syncthreads();
+  sync();
 }
 
 // Forces the values of all registers to be computed here.  Without it the
@@ -94,25 +128,25 @@ __device__ __forceinline__ void materialize(cpx<T>* r) {
 
 // Forward DIF sweep: natural order (stage-0 positions) in, digit-reversed
 // spectrum (last-stage positions) out.
-template <typename T, class F, bool MAT = true, int ST = 1>
+template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
 __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = decltype(tt)::value;
     F::template dif_stage<T, t>(reg, tau, tw);
-    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST>(reg, tau, lds);
+    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST, TW>(reg, tau, lds);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }
 
 // Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order out.
-template <typename T, class F, bool MAT = true, int ST = 1>
+template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
 __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = F::NS - 1 - decltype(tt)::value;
     F::template dit_stage<T, t>(reg, tau, tw);
-    if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST>(reg, tau, lds);
+    if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST, TW>(reg, tau, lds);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }

@@ -79,6 +79,15 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
                               const uint8_t* mask, double* z, const void* tw,
                               int n1, int n2, hipStream_t s);
 
+// Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
+// L = 2(n1+1) is also the convolution length): z = pass C output (stored),
+// t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL).
+template <typename T>
+hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2, const int* mirror,
+                                 const uint8_t* mask, double* z, double* t, const void* twT,
+                                 const void* tw64, const double* sym, double coef, double dpen,
+                                 const double* sub, double theta, int n1, int n2, hipStream_t s);
+
 // Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
 // power of two): T internals, tables chn (n entries) and khat (L entries, in
 // register-position order) per direction; W1 holds n1*n2 T values, Y1 and Y2

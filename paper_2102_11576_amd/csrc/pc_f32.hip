@@ -10,4 +10,8 @@ template hipError_t launch_pc_cols<float>(int, const float*, float*, float*, con
 template hipError_t launch_pc_rows_inv<float>(int, const float*, const float*, const int*,
                                             const uint8_t*, double*, const void*, int, int,
                                             hipStream_t);
+template hipError_t launch_pc_rows_inv_mv<float>(int, const float*, const float*, const int*,
+                                             const uint8_t*, double*, double*, const void*,
+                                             const void*, const double*, double, double,
+                                             const double*, double, int, int, hipStream_t);
 }  // namespace rsfde

@@ -10,4 +10,8 @@ template hipError_t launch_pc_cols<double>(int, const double*, double*, double*,
 template hipError_t launch_pc_rows_inv<double>(int, const double*, const double*, const int*,
                                             const uint8_t*, double*, const void*, int, int,
                                             hipStream_t);
+template hipError_t launch_pc_rows_inv_mv<double>(int, const double*, const double*, const int*,
+                                             const uint8_t*, double*, double*, const void*,
+                                             const void*, const double*, double, double,
+                                             const double*, double, int, int, hipStream_t);
 }  // namespace rsfde

@@ -221,6 +221,113 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
   });
 }
 
+// --------------------------------------------------------------------------
+// Pass C fused with the row pass of the matrix-vector product that follows it
+// in every Arnoldi step (w = M P_hat^{-1} v).  With n1 + 1 a power of two both
+// are row passes of one FFT length (2(n1+1) = next_pow2(2 n1)), so one block
+// takes a row pair through both: two inverse sweeps of pass C give z for rows
+// ra and rb (stored: the Krylov method keeps z, and the column pass reads it),
+// then one convolution on z_a + i z_b gives
+//   t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub.
+// z is placed at positions 1..n1 of the convolution (where pass C leaves it),
+// a circular shift that the convolution carries to its output.
+// --------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(PcCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4)))
+void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
+                      const int* __restrict__ mirror, const uint8_t* __restrict__ mask,
+                      double* __restrict__ z, double* __restrict__ t,
+                      const cpx<T>* __restrict__ twT, const cpx<double>* __restrict__ tw64,
+                      const double* __restrict__ sym, double coef, double dpen,
+                      const double* __restrict__ sub, double theta, int n1, int n2) {
+  using C = PcCfg<L>;
+  using F = typename C::F;
+  __shared__ double lds[C::BR * lds_len(L)];
+  const int tid = threadIdx.x;
+  const int b = tid / F::TPF, tau = tid % F::TPF;
+  const int pair = blockIdx.x * C::BR + b;
+  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const bool va = ra < n2, vb = rb < n2;
+  const int ld = n1 + 1;
+  double* my = lds + b * lds_len(L);
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    // opaque copies: no per-point address is hoisted out of the loop
+    const T* P1h = P1;
+    const T* P2h = P2;
+    const int* mih = mirror;
+    const cpx<T>* twh = twT;
+    double* zh = z;
+    const uint8_t* mh = mask;
+    int th = tau;
+    asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(mih), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
+    const int r = ra + h;
+    const bool vr = r < n2;
+    const T* p1 = P1h + (size_t)r * ld;
+    const T* p2 = P2h + (size_t)r * ld;
+    cpx<T> reg[F::PP];
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      constexpr int R = F::radix(F::NS - 1);
+      if constexpr ((e % R) < R / 2) {
+        const int slot = (th + (e / R) * F::TPF) * (R / 2) + (e % R);
+        reg[e].re = vr ? (T)0.5 * p2[slot] : (T)0;
+        reg[e].im = vr ? (T)-0.5 * p1[slot] : (T)0;
+      } else {
+        const int ms = mih[F::pos(F::NS - 1, th, e)];
+        const bool ok = vr && ms >= 0;
+        reg[e].re = ok ? (T)-0.5 * p2[ms] : (T)0;
+        reg[e].im = ok ? (T)0.5 * p1[ms] : (T)0;
+      }
+    });
+    fft_inverse<T, F>(reg, th, twh, reinterpret_cast<T*>(my));
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const int p = F::pos(0, th, e);
+      if (vr && p >= 1 && p <= n1) {
+        const size_t i = (size_t)r * n1 + (p - 1);
+        zh[i] = mh[i] ? (double)reg[e].re : (double)reg[e].im;
+      }
+    });
+  }
+  __threadfence_block();
+  __syncthreads();
+  cpx<double> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    const bool in = p >= 1 && p <= n1;
+    reg[e].re = (va && in) ? z[(size_t)ra * n1 + (p - 1)] : 0.0;
+    reg[e].im = (vb && in) ? z[(size_t)rb * n1 + (p - 1)] : 0.0;
+  });
+  fft_forward<double, F>(reg, tau, tw64, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const double sc = sym[F::pos(F::NS - 1, tau, e)] * coef;
+    reg[e].re *= sc;
+    reg[e].im *= sc;
+  });
+  fft_inverse<double, F>(reg, tau, tw64, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (p >= 1 && p <= n1) {
+      if (va) {
+        const size_t i = (size_t)ra * n1 + (p - 1);
+        double v = reg[e].re + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        if (sub) v -= theta * sub[i];
+        t[i] = v;
+      }
+      if (vb) {
+        const size_t i = (size_t)rb * n1 + (p - 1);
+        double v = reg[e].im + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        if (sub) v -= theta * sub[i];
+        t[i] = v;
+      }
+    }
+  });
+}
+
 // ------------------------------- launchers --------------------------------
 template <typename T, int L>
 static hipError_t pc_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* tw,
@@ -253,6 +360,21 @@ static hipError_t pc_rows_inv_impl(const T* P1, const T* P2, const int* mirror,
   const int blocks = (n2 + C::BR - 1) / C::BR;
   hipLaunchKernelGGL((k_pc_rows_inv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2, mirror,
                      mask, z, (const cpx<T>*)tw, n1, n2);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2, const int* mirror,
+                                      const uint8_t* mask, double* z, double* t, const void* twT,
+                                      const void* tw64, const double* sym, double coef,
+                                      double dpen, const double* sub, double theta, int n1,
+                                      int n2, hipStream_t s) {
+  using C = PcCfg<L>;
+  const int pairs = (n2 + 1) / 2;
+  const int blocks = (pairs + C::BR - 1) / C::BR;
+  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2, mirror,
+                     mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
+                     sub, theta, n1, n2);
   return hipGetLastError();
 }
 
@@ -296,6 +418,23 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
 #define X(LL) \
   case LL:    \
     return pc_rows_inv_impl<T, LL>(P1, P2, mirror, mask, z, tw, n1, n2, s);
+    RSFDE_LD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2, const int* mirror,
+                                 const uint8_t* mask, double* z, double* t, const void* twT,
+                                 const void* tw64, const double* sym, double coef, double dpen,
+                                 const double* sub, double theta, int n1, int n2, hipStream_t s) {
+  switch (L) {
+#define X(LL) \
+  case LL:    \
+    return pc_rows_inv_mv_impl<T, LL>(P1, P2, mirror, mask, z, t, twT, tw64, sym, coef, dpen, sub, \
+                                      theta, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:

@@ -182,13 +182,13 @@ hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
 enum ProfCat {
   kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
   kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kCatCdRows, kCatCdCols,
-  kCatCdRowsInv, kCatGram, kCatBupd, kNumCats
+  kCatCdRowsInv, kCatGram, kCatBupd, kCatPcInvMv, kNumCats
 };
 const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
                                          "pc_rows_inv", "multidot", "axpy_givens", "update",
                                          "residual", "rhs", "other", "pc_gemm_bf16",
                                          "cd_rows_fwd", "cd_cols", "cd_rows_inv", "block_gram",
-                                         "block_update"};
+                                         "block_update", "pc_inv_mv_rows"};
 
 // Brackets one kernel launch with timing events when profiling is on.
 struct ProfScope {
@@ -475,6 +475,65 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
   return RSFDE_EUNSUPPORTED;
 }
 
+// w = M P_hat^{-1} (sig v) - theta sub, z = P_hat^{-1} (sig v) (stored): the
+// preconditioner's last pass and the matrix-vector row pass run as one kernel
+// when n1 + 1 and n2 + 1 are powers of two (FP64 / FP32 internals); otherwise
+// the two operators run one after the other.
+int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, double* w,
+                        int precision, hipStream_t s, const double* sub = nullptr,
+                        double theta = 0.0) {
+  const bool fused = P->Ldx && P->Ldy && P->Ldx == P->Lcx &&
+                     (precision == RSFDE_FP64 || precision == RSFDE_FP32);
+  if (!fused) {
+    int rc = precond_impl(P, v, sig, z, precision, s);
+    if (rc) return rc;
+    return matvec_impl(P, z, w, s, sub, theta);
+  }
+  const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
+  const double N = (double)P->N, S = (double)(P->n1 + 1) * (double)P->n2;
+  const double extra = sub ? 8.0 * N : 0.0;
+  if (precision == RSFDE_FP64) {
+    double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
+    {
+      ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
+      CK(launch_pc_rows_fwd<double>(P->Ldx, v, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcCols, 24.0 * S);
+      CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcInvMv, 16.0 * S + 17.0 * N + extra);
+      CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->t,
+                                       P->tw64[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
+                                       sub, theta, P->n1, P->n2, s));
+    }
+  } else {
+    float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
+    {
+      ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
+      CK(launch_pc_rows_fwd<float>(P->Ldx, v, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcCols, 12.0 * S);
+      CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+    }
+    {
+      ProfScope ps(P, s, kCatPcInvMv, 8.0 * S + 17.0 * N + extra);
+      CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->t,
+                                      P->tw32[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
+                                      sub, theta, P->n1, P->n2, s));
+    }
+  }
+  {
+    ProfScope ps(P, s, kCatMvCols, 24.0 * N);
+    CK(launch_mv_cols(P->Lcy, z, P->t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+  }
+  return RSFDE_OK;
+}
+
 int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (!o) return RSFDE_EINVAL;
   if (o->restart < 1 || o->restart > P->max_restart) return RSFDE_EINVAL;
@@ -582,14 +641,16 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
         wv = zj;
       } else {  // z_j = P_hat^{-1} v_j, w = M z_j
         if (tau) {
-          rc = precond_impl(P, vj, sig, zj, o->precision, s);
+          rc = precond_matvec_impl(P, vj, sig, zj, P->w, o->precision, s);
           if (rc) return finish(st, rc, total, cycles, beta, bnorm);
         } else {
-          ProfScope ps(P, s, kCatOther, 16.0 * N);
-          CK(launch_scale_copy(vj, sig, zj, N, s));
+          {
+            ProfScope ps(P, s, kCatOther, 16.0 * N);
+            CK(launch_scale_copy(vj, sig, zj, N, s));
+          }
+          rc = matvec_impl(P, zj, P->w, s);
+          if (rc) return finish(st, rc, total, cycles, beta, bnorm);
         }
-        rc = matvec_impl(P, zj, P->w, s);
-        if (rc) return finish(st, rc, total, cycles, beta, bnorm);
       }
       double* vnext = P->V + (size_t)(j + 1) * ld;
       {
@@ -788,9 +849,8 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
       for (int i = 0; i < ss; ++i) {
         double* ui = P->V + (size_t)(m + i) * ld;
         double* zi = P->Z + (size_t)(m + i) * ld;
-        rc = precond_impl(P, ui, nullptr, zi, o->precision, s);
-        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
-        rc = matvec_impl(P, zi, P->V + (size_t)(m + i + 1) * ld, s, ui, theta);
+        rc = precond_matvec_impl(P, ui, nullptr, zi, P->V + (size_t)(m + i + 1) * ld, o->precision,
+                                 s, ui, theta);
         if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
       }
       const int nq = m + 1;

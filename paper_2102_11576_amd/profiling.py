@@ -38,6 +38,7 @@ FAMILIES = [
     (r"k_pc_rows_fwd<", "pc_rows_fwd"),
     (r"k_pc_cols<", "pc_cols"),
     (r"k_pc_rows_inv<", "pc_rows_inv"),
+    (r"k_pc_rows_inv_mv<", "pc_inv_mv_rows"),
     (r"k_gemm_bf16", "pc_gemm_bf16"),
     (r"k_residual\b", "residual"),
     (r"k_rhs\b", "rhs"),
@@ -131,6 +132,8 @@ def _alg_bytes(name: str, n1: int, n2: int) -> float:
         return 3.0 * ts * S
     if "k_pc_rows_inv<" in name:
         return 2.0 * ts * S + 9.0 * N
+    if "k_pc_rows_inv_mv<" in name:  # with the s-step shift term read (sub)
+        return 2.0 * ts * S + 25.0 * N
     return 0.0
 
 
