@@ -45,56 +45,42 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  const size_t nchunks = N / 8;  // 8 elements per wave step
+  // Chunks of 32 elements: lane group k4 owns elements base + 8 k4 .. + 7 of
+  // every row (64 contiguous bytes per lane, 256 per row), and MFMA step j
+  // takes element base + 8 k4 + j for A and B alike.
+  const size_t nchunks = N / 32;
   const size_t gw = (size_t)gridDim.x * 4;
-  size_t ch = (size_t)blockIdx.x * 4 + wid;
-  // four chunks per iteration: all loads issued before the products, so each
-  // wave keeps 4 (NT + 1) 16-byte loads per lane in flight
-  constexpr int UR = 4;
-  for (; ch + (UR - 1) * gw < nchunks; ch += UR * gw) {
-    double2 b[UR], a[UR][NT];
+  for (size_t ch = (size_t)blockIdx.x * 4 + wid; ch < nchunks; ch += gw) {
+    const size_t e = ch * 32 + 8 * k4;
+    double2 b[4], a[NT][4];
 #pragma unroll
-    for (int u = 0; u < UR; ++u) {
-      const size_t e = (ch + u * gw) * 8 + 2 * k4;
-      b[u] = bvalid ? *reinterpret_cast<const double2*>(brow + e) : double2{0.0, 0.0};
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        a[u][t] = avalid[t] ? *reinterpret_cast<const double2*>(arow[t] + e) : double2{0.0, 0.0};
-    }
-#pragma unroll
-    for (int u = 0; u < UR; ++u)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t].x, b[u].x, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t].y, b[u].y, acc[t], 0, 0, 0);
-      }
-  }
-  for (; ch < nchunks; ch += gw) {
-    const size_t e = ch * 8 + 2 * k4;
-    const double2 b = bvalid ? *reinterpret_cast<const double2*>(brow + e) : double2{0.0, 0.0};
-    double2 a[NT];
+    for (int q = 0; q < 4; ++q)
+      b[q] = bvalid ? reinterpret_cast<const double2*>(brow + e)[q] : double2{0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      a[t] = avalid[t] ? *reinterpret_cast<const double2*>(arow[t] + e) : double2{0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b.x, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].y, b.y, acc[t], 0, 0, 0);
-    }
+      for (int q = 0; q < 4; ++q)
+        a[t][q] = avalid[t] ? reinterpret_cast<const double2*>(arow[t] + e)[q] : double2{0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][q].x, b[q].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][q].y, b[q].y, acc[t], 0, 0, 0);
+      }
   }
-  // tail (N % 8 elements): block 0, wave 0 only
+  // tail (N % 32 elements): block 0, wave 0 only
   if (blockIdx.x == 0 && wid == 0) {
-    const size_t e0 = nchunks * 8 + 2 * k4;
-    double2 b = {0.0, 0.0};
-    if (bvalid && e0 < N) b.x = brow[e0];
-    if (bvalid && e0 + 1 < N) b.y = brow[e0 + 1];
+    const size_t e0 = nchunks * 32 + 8 * k4;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      double2 a = {0.0, 0.0};
-      if (avalid[t] && e0 < N) a.x = arow[t][e0];
-      if (avalid[t] && e0 + 1 < N) a.y = arow[t][e0 + 1];
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc[t], 0, 0, 0);
+    for (int j = 0; j < 8; ++j) {
+      const size_t e = e0 + j;
+      const double bv = (bvalid && e < N) ? brow[e] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double av = (avalid[t] && e < N) ? arow[t][e] : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -208,7 +194,7 @@ __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, si
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, hipStream_t st) {
   if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
-  int nb = (int)((N / 8 + 4 * 16 - 1) / (4 * 16));  // >= 16 chunks per wave
+  int nb = (int)((N / 32 + 4 * 4 - 1) / (4 * 4));  // >= 4 chunks per wave
   if (nb < 1) nb = 1;
   if (nb > kGramBlocks) nb = kGramBlocks;
   const int nt = (nr + 15) / 16;
