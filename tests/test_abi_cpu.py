@@ -90,3 +90,29 @@ def test_fft_engine_selftest():
     exe = build_selftest()
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout
+
+
+def test_new_entry_points_validate_on_the_host(lib):
+    """rsfde_step_src and rsfde_march_ensemble reject bad arguments before any
+    device work (no GPU needed): NULL plans, empty ensembles, NULL arrays."""
+    from paper_2102_11576_amd._lib import rsfde_solver_opts, rsfde_stats
+    P = C.c_void_p
+    fake = C.c_void_p(0x1000)
+    st = rsfde_stats()
+    o = rsfde_solver_opts(20, 100, 1e-8, 0, 0, 0, 0, 0)
+    lib.rsfde_step_src.argtypes = [P, P, P, C.c_int32, P, C.c_double,
+                                   C.POINTER(rsfde_solver_opts), P, C.POINTER(rsfde_stats), P]
+    assert lib.rsfde_step_src(None, fake, None, 4, fake, 1.0, C.byref(o), fake, C.byref(st),
+                              None) == -1
+    assert st.status == -1
+    PP = C.POINTER(C.c_void_p)
+    lib.rsfde_march_ensemble.argtypes = [C.c_int32, PP, PP, C.c_int32, C.c_int32,
+                                         C.POINTER(rsfde_solver_opts), PP, PP,
+                                         C.POINTER(rsfde_stats), PP]
+    arr = (C.c_void_p * 2)(0x1000, 0x2000)
+    assert lib.rsfde_march_ensemble(0, arr, arr, 1, 0, C.byref(o), arr, arr, None, None) == -1
+    assert lib.rsfde_march_ensemble(1, None, arr, 1, 0, C.byref(o), arr, arr, None, None) == -1
+    assert lib.rsfde_march_ensemble(1, arr, arr, -1, 0, C.byref(o), arr, arr, None, None) == -1
+    assert lib.rsfde_march_ensemble(1, arr, arr, 1, 9, C.byref(o), arr, arr, None, None) == -1
+    nul = (C.c_void_p * 2)(None, None)
+    assert lib.rsfde_march_ensemble(1, nul, arr, 1, 0, C.byref(o), arr, arr, None, None) == -1

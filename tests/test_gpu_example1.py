@@ -159,3 +159,21 @@ def test_first_order_convergence_at_larger_n():
     assert 1.6 < r1 < 2.4 and 1.6 < r2 < 2.4, errs
     err_r, _, _, _, _ = _ex1_gpu(256, 1.0, side="right")
     assert err_r == pytest.approx(errs[1], rel=1e-3)
+
+
+def test_paper_mode_fp32_preconditioner():
+    """Paper mode with FP32 internals of the preconditioner (chirp form at
+    n = 64): Table 1's error is kept and the mean Iter stays within 0.1."""
+    row = [r for r in GOLD["table1"]["rows"] if r["kx"] == 1.0 and r["n1"] == 64][0]
+    w = example1_workload(64, 1.0)
+    dt = w.T / w.m
+    with RsfdePlan.from_workload(w) as pl:
+        u, iters, _ = pl.march(_t(w.u0), w.m, w.f_kind,
+                               make_opts(w.restart, 10000, w.tol, "fp32", side="left"),
+                               src=_t(w.extra["src"]), src_scale=lambda k: math.exp(-(k - 1) * dt))
+        u = u.cpu().numpy().reshape(64, 64)
+    ue = math.exp(-w.T) * w.extra["exact0"]
+    inside = w.mask.astype(bool)
+    err = np.abs(ue - u)[inside].max() / np.abs(ue)[inside].max()
+    assert err == pytest.approx(row["gmres_err"], rel=0.03)
+    assert abs(np.mean(iters) - row["pgmres_iter"]) <= 0.1

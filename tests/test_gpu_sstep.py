@@ -90,3 +90,15 @@ def test_sstep_full_size_2047_true_residual(s, precision):
     assert np.linalg.norm(r) <= (w.tol + 1e-12) * np.linalg.norm(b)
     assert st.relres <= w.tol
     assert 40 < st.iters < 300
+
+
+def test_sstep_iteration_cap_and_nonfinite_input():
+    w = make_config("c4", n=71, m=1)
+    with RsfdePlan.from_workload(w) as pl:
+        u0 = _t(w.u0)
+        _, st = pl.step(u0, None, w.f_kind, make_opts(30, 5, 1e-14, sstep=4), check=False)
+        assert st.status == rsfde._lib.RSFDE_ENOTCONV and st.iters == 5
+        bad = u0.clone()
+        bad[17] = float("nan")
+        _, st = pl.step(bad, None, w.f_kind, make_opts(30, 100, 1e-8, sstep=4), check=False)
+        assert st.status == rsfde._lib.RSFDE_ENONFINITE
