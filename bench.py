@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--mode", choices=["march", "kernels"], default="march",
+    ap.add_argument("--mode", choices=["march", "kernels", "ablations"], default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-ensemble", action="store_true")
@@ -274,10 +274,50 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def ablations(args):
+    """Arnoldi-traffic ablations on the benchmark march (FP64 preconditioner,
+    tol 1e-8): GMRES form (one-vector CGS, CGS2, s-step s = 2..16) and restart
+    length, each timed over the same steps.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from workloads.configs import make_config
+    w = make_config(args.workload, n=args.n)
+    K = min(w.m, args.steps or 8)
+    dev = torch.device("cuda:0")
+    plan = RsfdePlan.from_workload(w, max_restart=64, device=dev)
+    u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+
+    def run(restart, sstep, reorth=0):
+        opts = make_opts(restart, 100000, w.tol, "fp64", reorth=reorth, sstep=sstep)
+        plan.march(u0, 1, w.f_kind, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, _ = plan.march(u0, K, w.f_kind, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        row = {"restart": restart, "sstep": sstep, "reorth": reorth, "ms_per_step": 1e3 * dt / K,
+               "gmres_iters_per_step": float(np.mean(it))}
+        log(f"ablation restart {restart} sstep {sstep} reorth {reorth}: "
+            f"{row['ms_per_step']:.2f} ms/step, {row['gmres_iters_per_step']:.1f} it/step")
+        return row
+    rows = [run(w.restart, 0, -1), run(w.restart, 0, 1)]
+    rows += [run(w.restart, s) for s in (2, 4, 8, 16)]
+    rows += [run(r, 8) for r in (10, 20, 40, 60)]
+    rows += [run(r, 0, -1) for r in (10, 20, 40, 60)]
+    plan.close()
+    print(json.dumps({"ablations": rows, "workload": w.name, "n": w.n1, "steps": K,
+                      "note": "sstep 0 = one Arnoldi vector per step (reorth -1: one CGS pass, "
+                              "1: two); sstep s >= 2 = s-step blocks"}))
+
+
 def main():
     args = parse()
     if args.mode == "kernels":
         kernel_mode(args)
+        return
+    if args.mode == "ablations":
+        ablations(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
