@@ -320,8 +320,8 @@ def main():
         ablations(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
-                                   "design-only (see DESIGN.md). Use --gpus 1."}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the grid "
+                                   "over several GPUs is not implemented. Use --gpus 1."}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -400,7 +400,7 @@ def main():
         d = float((u32 - u64).abs().max() / u64.abs().max())
         # BF16 preconditioner: bounded to the first KB steps.  At this stiffness the
         # flexible GMRES stalls from step 3 on (BF16 rounding of the preconditioned
-        # vector is amplified by ||M|| ~ 1e5; see DESIGN.md), so the full march is
+        # vector is amplified by ||M|| ~ 1e5), so the full march is
         # not run here.
         KB = min(2, K)
         u64b, _, _, _ = timed_march("fp64", KB, sstep=0)

@@ -193,7 +193,7 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
                        void* stream);
 
 /* Advance an ensemble of independent plans (finite-difference directions,
- * parameter sweeps, several initial fields; SURVEY's batched solves) by m
+ * parameter sweeps, several initial fields: batched solves) by m
  * implicit steps each (rsfde_step semantics: initial guess 2u^{k-1} - u^{k-2},
  * f_kind, opts), concurrently: one host thread per plan, each enqueueing on
  * streams[i] (or that plan's set-up stream when streams is NULL).  Members

@@ -9,7 +9,7 @@ the HIP library, so both sides see bit-identical inputs.
 Array layout: row-major [n2][n1] (x fastest), matching the lexicographic
 ordering of the unknowns in Section 2 of the paper.
 
-Unstated details are fixed as follows (listed again in the design doc):
+Unstated details are fixed as follows:
   * all domains are centred at (0.5, 0.5) inside the box [0,1]^2, T = 1;
   * a grid point exactly on the boundary counts as inside (closed domain);
   * a Gaussian bump is A*exp(-((x-cx)^2+(y-cy)^2)/(2 w^2));
