@@ -7,3 +7,4 @@ this package imports nothing from the product path.
 """
 
 from .rsfde_oracle import *  # noqa: F401,F403
+from .rsfde_oracle3d import *  # noqa: F401,F403

@@ -17,3 +17,4 @@ from .configs import (  # noqa: F401
     example1_workload,
 )
 from .example1 import example1_exact, example1_source_field  # noqa: F401
+from .three_d import Workload3, make_config3d, ellipsoid_mask, interior_coords3  # noqa: F401
