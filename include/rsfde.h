@@ -1,7 +1,8 @@
 /*
  * rsfde.h — C ABI of the MI355X (gfx950) solver for the volume-penalized
  * implicit finite-difference system of the 2-D Riesz space-fractional
- * diffusion equation, preconditioned by the sine-transform (tau) matrices.
+ * diffusion equation, preconditioned by the sine-transform (tau) matrices
+ * (and its 3-D form, rsfde_setup3).
  *
  * Paper: X. Huang, H.-W. Sun, "A preconditioner based on sine transform for
  * two-dimensional Riesz space fractional diffusion equations in convex
@@ -128,8 +129,35 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
                 double kx, double ky, const uint8_t* mask_dev, double eta, double dt,
                 int32_t max_restart, void* stream);
 
+/* Three-dimensional plans.  The paper treats two dimensions and leaves higher
+ * dimensions to future work (concluding section); this plan carries Section 2
+ * and Section 4.1 over with a third Kronecker factor:
+ *   M = I - (I (x) I (x) A_x + I (x) A_y (x) I + A_z (x) I (x) I) + D,
+ *   P_hat^{-1} = mask (S (x) S (x) S)(I - Lx - Ly - Lz)^{-1}(S (x) S (x) S)
+ *              + (1 - mask) (S (x) S (x) S)((1 + dt/eta) I - Lx - Ly - Lz)^{-1}(S (x) S (x) S)
+ * with A_z = c_z G^(alpha3), c_z = dt kz c_alpha3 / h_z^alpha3, and the tau
+ * eigenvalues along each axis.  Vectors and the mask are [n3][n2][n1] (x
+ * fastest), N = n1 n2 n3.  n1+1, n2+1 and n3+1 must be powers of two (each
+ * n <= 4095; EUNSUPPORTED otherwise) and (n1+1) n2 n3 < 2^31.
+ * rsfde_matvec, rsfde_precond_apply (FP64 / FP32), rsfde_step, rsfde_step_src,
+ * rsfde_solve and rsfde_march_ensemble accept a 3-D plan; rsfde_set_coeffs,
+ * rsfde_adjoint_step and the BF16 preconditioner return EUNSUPPORTED for it.
+ * The plan owns four preconditioner intermediates of (n1+1) n2 n3 doubles and
+ * one more vector than a 2-D plan.  Other arguments as rsfde_setup.
+ * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED. */
+typedef struct {
+  int32_t n1, n2, n3;       /* interior points in x, y, z, >= 1 */
+  double x_lo, x_hi;
+  double y_lo, y_hi;
+  double z_lo, z_hi;        /* box in z, z_hi > z_lo */
+} rsfde_grid3;
+
+int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double alpha2,
+                 double alpha3, double kx, double ky, double kz, const uint8_t* mask_dev,
+                 double eta, double dt, int32_t max_restart, void* stream);
+
 /* Change kx, ky (O(1): the symbols and eigenvalues are stored for k = 1 and
- * scaled at apply time).  Errors: EINVAL. */
+ * scaled at apply time).  Errors: EINVAL, EUNSUPPORTED (3-D plan). */
 int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky);
 
 /* y = M x with M = I - A + D, A = I (x) A_x + A_y (x) I (matrix_vector,

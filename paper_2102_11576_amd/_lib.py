@@ -37,6 +37,13 @@ class rsfde_grid(C.Structure):
                 ("y_lo", C.c_double), ("y_hi", C.c_double)]
 
 
+class rsfde_grid3(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("y_lo", C.c_double), ("y_hi", C.c_double),
+                ("z_lo", C.c_double), ("z_hi", C.c_double)]
+
+
 class rsfde_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("reorth", C.c_int32),
@@ -67,6 +74,9 @@ def _load():
     P = C.c_void_p
     lib.rsfde_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,
                                 C.c_double, C.c_double, P, C.c_double, C.c_double, C.c_int32, P]
+    lib.rsfde_setup3.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid3), C.c_double, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.c_double, P, C.c_double,
+                                 C.c_double, C.c_int32, P]
     lib.rsfde_set_coeffs.argtypes = [P, C.c_double, C.c_double]
     lib.rsfde_matvec.argtypes = [P, P, P, P]
     lib.rsfde_precond_apply.argtypes = [P, P, P, C.c_int32, P]
@@ -87,7 +97,7 @@ def _load():
     lib.rsfde_destroy.argtypes = [P]
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
-    for f in ("rsfde_setup", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
+    for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
               "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_march_ensemble", "rsfde_adjoint_step", "rsfde_destroy",
               "rsfde_profile", "rsfde_profile_read"):
         getattr(lib, f).restype = C.c_int
@@ -158,6 +168,21 @@ def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=
                           float(ky), _ptr(mask), float(eta), float(dt), int(max_restart),
                           _stream(stream))
     _raise(rc, "rsfde_setup")
+    return h
+
+
+def rsfde_setup3(n, box, alphas, ks, mask, eta, dt, max_restart=30, stream=None):
+    """n = (n1, n2, n3), box = (x_lo, x_hi, y_lo, y_hi, z_lo, z_hi), alphas and ks
+    per axis; mask is a uint8 GPU tensor of n1*n2*n3 entries ([n3][n2][n1])."""
+    import torch
+    n1, n2, n3 = (int(v) for v in n)
+    _check_vec(mask, n1 * n2 * n3, "mask", torch.uint8)
+    g = rsfde_grid3(n1, n2, n3, *(float(v) for v in box))
+    h = C.c_void_p()
+    rc = _lib.rsfde_setup3(C.byref(h), C.byref(g), *(float(a) for a in alphas),
+                           *(float(k) for k in ks), _ptr(mask), float(eta), float(dt),
+                           int(max_restart), _stream(stream))
+    _raise(rc, "rsfde_setup3")
     return h
 
 

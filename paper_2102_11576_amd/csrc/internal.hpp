@@ -57,10 +57,12 @@ hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* o
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, double dpen, int mode, hipStream_t s,
                           const double* sub = nullptr, double theta = 0.0);
-// Column pass: out = coef * (C_y z) + (mode==0 ? t : 0).
+// Column pass: out = coef * (C_y z) + (mode==0 ? t : 0) on `batch` [n2][n1]
+// slices, slice b at offset b * bstride of z, t and out.
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2,
-                          double coef, int mode, hipStream_t s);
+                          double coef, int mode, hipStream_t s, int batch = 1,
+                          size_t bstride = 0);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
 // Pass A: Q[r][slot] = raw x-sine sums of (sig * v) rows.
@@ -73,6 +75,16 @@ template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2,
                           double kx, double ky, double dpen, double Kfac, hipStream_t s);
+// Raw sine transform (DST-I without normalisation) along the columns of
+// `batch` slices of [rows][ld] values (slice b at offset b * bstride):
+//   outA[k-1][ca] = sum_{p=1..rows} inA[p-1][ca] sin(pi k p / (rows + 1)), k = 1..rows,
+// and likewise inB column cb -> outB, with ca = c * cstride, cb = ca + coff for
+// c = 0..ncol-1 (cstride 2, coff 1: adjacent column pairs of one array;
+// cstride 1, coff 0: the same column of two arrays).  L = 2 (rows + 1).
+template <typename T>
+hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, const void* tw,
+                           int ncol, int cstride, int coff, int rows, int ld, int batch,
+                           size_t bstride, hipStream_t s);
 // Pass C: inverse row transforms of P1, P2 and the mask combine -> z (FP64).
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirror,

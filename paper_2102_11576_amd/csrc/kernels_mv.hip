@@ -3,6 +3,8 @@
 // penalty diagonal dt/eta outside the domain), in two HBM passes:
 //   row pass:    t = (1 + dpen*phi) z - kx * (Ahat_x applied along x)
 //   column pass: w = t - ky * (Ahat_y applied along y)
+// A third dimension adds one more column pass (z lines are the columns of the
+// [n3][n1*n2] view) and runs the y pass once per z slice (grid dimension y).
 // Each Toeplitz product is a circular convolution of length L >= 2n-1 with the
 // real, even symbol of the circulant embedding [t_0..t_{n-1}, 0.., t_{n-1}..t_1]
 // (O(N log N) per product, the fast matrix-vector product the paper relies on).
@@ -82,16 +84,23 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu
 // --------------------------------------------------------------------------
 // Column pass.  Block = BC FFTs over 2*BC adjacent columns; thread layout is
 // (tau, b) with b fastest so that a wavefront reads 2*BC contiguous doubles of
-// several rows at once.
+// several rows at once.  blockIdx.y selects a [n2][n1] slice at offset
+// blockIdx.y * bstride (one slice in two dimensions).
 // --------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_cols(
     const double* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
-    double coef, int mode) {
+    double coef, int mode, size_t bstride) {
   using C = MvCfg<L>;
   using F = typename C::F;
   __shared__ double lds[C::BC * lds_len(L)];
+  {
+    const size_t off = (size_t)blockIdx.y * bstride;
+    z += off;
+    out += off;
+    if (mode == 0) t += off;
+  }
   const int tid = threadIdx.x;
   const int b = tid % C::BC, tau = tid / C::BC;
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
@@ -145,12 +154,14 @@ static hipError_t mv_rows_impl(const double* z, const uint8_t* mask, double* out
 
 template <int L>
 static hipError_t mv_cols_impl(const double* z, const double* t, double* out, const double* sym,
-                               const void* tw, int n1, int n2, double coef, int mode, hipStream_t s) {
+                               const void* tw, int n1, int n2, double coef, int mode, hipStream_t s,
+                               int batch, size_t bstride) {
   using C = MvCfg<L>;
   const int pairs = (n1 + 1) / 2;
   const int blocks = (pairs + C::BC - 1) / C::BC;
-  hipLaunchKernelGGL(k_mv_cols<L>, dim3(blocks), dim3(C::THR_C), 0, s, z, t, out, sym,
-                     (const cpx<double>*)tw, n1, n2, coef, mode);
+  if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mv_cols<L>, dim3(blocks, batch), dim3(C::THR_C), 0, s, z, t, out, sym,
+                     (const cpx<double>*)tw, n1, n2, coef, mode, bstride);
   return hipGetLastError();
 }
 
@@ -173,11 +184,11 @@ hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* o
 
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,
-                          int mode, hipStream_t s) {
+                          int mode, hipStream_t s, int batch, size_t bstride) {
   switch (L) {
 #define X(LL) \
   case LL:    \
-    return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s);
+    return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s, batch, bstride);
     RSFDE_L_CASES(X)
 #undef X
     default:

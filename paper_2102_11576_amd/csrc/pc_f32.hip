@@ -14,4 +14,6 @@ template hipError_t launch_pc_rows_inv_mv<float>(int, const float*, const float*
                                              const uint8_t*, double*, double*, const void*,
                                              const void*, const double*, double, double,
                                              const double*, double, int, int, hipStream_t);
+template hipError_t launch_dst_cols<float>(int, const float*, const float*, float*, float*, const void*, int,
+                                          int, int, int, int, int, size_t, hipStream_t);
 }  // namespace rsfde

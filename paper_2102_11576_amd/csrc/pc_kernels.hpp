@@ -176,6 +176,62 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
 }
 
 // --------------------------------------------------------------------------
+// Raw sine transform along columns (used between the x and z transforms of
+// the three-dimensional preconditioner, where the y transform stands alone).
+// One FFT of length L = 2(rows+1) per column pair: column ca of inA in the
+// real part, column cb of inB in the imaginary part, both odd-extended; the
+// spectrum is 2 sigma_b - 2i sigma_a, read at frequencies 1..rows.
+// --------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_dst_cols(
+    const T* __restrict__ inA, const T* __restrict__ inB, T* __restrict__ outA,
+    T* __restrict__ outB, const cpx<T>* __restrict__ tw, int ncol, int cstride, int coff,
+    int rows, int ld, size_t bstride) {
+  using C = PcColCfg<L>;
+  using F = typename C::F;
+  __shared__ T lds[C::BC * lds_len(L)];
+  {
+    const size_t off = (size_t)blockIdx.y * bstride;
+    inA += off;
+    inB += off;
+    outA += off;
+    outB += off;
+  }
+  const int tid = threadIdx.x;
+  const int b = tid % C::BC, tau = tid / C::BC;
+  const int c = xcd_remap(blockIdx.x, gridDim.x) * C::BC + b;
+  const bool valid = c < ncol;
+  const int ca = c * cstride, cb = ca + coff;
+  cpx<T> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    int row = -1;
+    T sgn = (T)1;
+    if (p >= 1 && p <= rows) {
+      row = p - 1;
+    } else if (p >= rows + 2) {
+      row = L - p - 1;
+      sgn = (T)-1;
+    }
+    const bool ok = valid && row >= 0;
+    reg[e].re = ok ? sgn * inA[(size_t)row * ld + ca] : (T)0;
+    reg[e].im = ok ? sgn * inB[(size_t)row * ld + cb] : (T)0;
+  });
+  T* my = lds + b;  // regions interleaved (stride BC)
+  fft_forward<T, F, false, C::BC>(reg, tau, tw, my);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int f = fft_freq(L, pc_cols_pts(L), F::pos(F::NS - 1, tau, e));
+    if (valid && f >= 1 && f <= rows) {
+      const size_t i = (size_t)(f - 1) * ld;
+      outA[i + ca] = (T)-0.5 * reg[e].im;
+      outB[i + cb] = (T)0.5 * reg[e].re;
+    }
+  });
+}
+
+// --------------------------------------------------------------------------
 // Pass C: one row r per FFT; spectrum P2/2 - i P1/2 on the lower half, odd
 // mirror on the upper half; the inverse sweep gives (P1 S_x) + i (P2 S_x).
 // --------------------------------------------------------------------------
@@ -378,6 +434,18 @@ static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2, const int* mirro
   return hipGetLastError();
 }
 
+template <typename T, int L>
+static hipError_t dst_cols_impl(const T* inA, const T* inB, T* outA, T* outB, const void* tw,
+                                int ncol, int cstride, int coff, int rows, int ld, int batch,
+                                size_t bstride, hipStream_t s) {
+  using C = PcColCfg<L>;
+  if (L != 2 * (rows + 1) || batch < 1 || batch > 65535 || ncol < 1) return hipErrorInvalidValue;
+  const int blocks = (ncol + C::BC - 1) / C::BC;
+  hipLaunchKernelGGL((k_dst_cols<T, L>), dim3(blocks, batch), dim3(C::THR_C), 0, s, inA, inB, outA,
+                     outB, (const cpx<T>*)tw, ncol, cstride, coff, rows, ld, bstride);
+  return hipGetLastError();
+}
+
 #define RSFDE_LD_CASES(X) \
   X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
@@ -403,6 +471,22 @@ hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
 #define X(LL) \
   case LL:    \
     return pc_cols_impl<T, LL>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, dpen, Kfac, s);
+    RSFDE_LD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, const void* tw,
+                           int ncol, int cstride, int coff, int rows, int ld, int batch,
+                           size_t bstride, hipStream_t s) {
+  switch (L) {
+#define X(LL) \
+  case LL:    \
+    return dst_cols_impl<T, LL>(inA, inB, outA, outB, tw, ncol, cstride, coff, rows, ld, batch, \
+                                bstride, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:

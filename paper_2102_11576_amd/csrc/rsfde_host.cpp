@@ -77,6 +77,19 @@ struct Plan {
   int Lcx = 0, Lcy = 0, Ldx = 0, Ldy = 0;
   int Lgx = 0, Lgy = 0;  // chirp-DST convolution lengths (0: power-of-two path)
   int max_restart = 0;
+  // three-dimensional plans (rsfde_setup3), arrays [n3][n2][n1]; n3 may be 1
+  // (A_z is then the 1 x 1 matrix c_z 2 g_1, not absent)
+  bool is3d = false;
+  int n3 = 1;
+  double alpha3 = 0, kz = 0;
+  int Lcz = 0, Ldz = 0;
+  double* symz = nullptr;
+  double* lamz64 = nullptr;  // z eigenvalues (unit kz), register-position order of Ldz
+  float* lamz32 = nullptr;
+  double* lamc64 = nullptr;  // kx lx(slot) + ky ly(j) for the column j * (n1+1) + slot
+  float* lamc32 = nullptr;
+  void* R3 = nullptr;        // preconditioner intermediate (y-transformed)
+  double* t3 = nullptr;      // matrix-vector intermediate (after the y pass)
 
   uint8_t* mask = nullptr;
   double* V = nullptr;
@@ -182,13 +195,13 @@ hipStream_t pick(Plan* P, void* s) { return s ? (hipStream_t)s : P->s0; }
 enum ProfCat {
   kCatMvRows, kCatMvCols, kCatPcRows, kCatPcCols, kCatPcRowsInv, kCatMultidot, kCatAxpy,
   kCatUpdate, kCatResidual, kCatRhs, kCatOther, kCatPcGemm, kCatCdRows, kCatCdCols,
-  kCatCdRowsInv, kCatGram, kCatBupd, kCatPcInvMv, kNumCats
+  kCatCdRowsInv, kCatGram, kCatBupd, kCatPcInvMv, kCatDstCols, kNumCats
 };
 const char* const kCatNames[kNumCats] = {"mv_rows", "mv_cols", "pc_rows_fwd", "pc_cols",
                                          "pc_rows_inv", "multidot", "axpy_givens", "update",
                                          "residual", "rhs", "other", "pc_gemm_bf16",
                                          "cd_rows_fwd", "cd_cols", "cd_rows_inv", "block_gram",
-                                         "block_update", "pc_inv_mv_rows"};
+                                         "block_update", "pc_inv_mv_rows", "dst_cols"};
 
 // Brackets one kernel launch with timing events when profiling is on.
 struct ProfScope {
@@ -380,10 +393,36 @@ hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
   return hipSuccess;
 }
 
+// The y and z passes of the three-dimensional product: t3 = t - ky (A_y along
+// y) x slice by slice, then y = t3 - kz (A_z along z) x on the [n3][n1*n2] view.
+int matvec_cols3(Plan* P, const double* x, double* y, hipStream_t s) {
+  const double N = (double)P->N;
+  const int plane = P->n1 * P->n2;
+  {
+    ProfScope ps(P, s, kCatMvCols, 24.0 * N);
+    CK(launch_mv_cols(P->Lcy, x, P->t, P->t3, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s,
+                      P->n3, (size_t)plane));
+  }
+  {
+    ProfScope ps(P, s, kCatMvCols, 24.0 * N);
+    CK(launch_mv_cols(P->Lcz, x, P->t3, y, P->symz, P->tw64[P->Lcz], plane, P->n3, -P->kz, 0, s));
+  }
+  return RSFDE_OK;
+}
+
 // y = M x - theta * sub (sub = NULL: y = M x).
 int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s, const double* sub = nullptr,
                 double theta = 0.0) {
   const double N = (double)P->N;
+  if (P->is3d) {
+    const int rows = P->n2 * P->n3;
+    {
+      ProfScope ps(P, s, kCatMvRows, (sub ? 25.0 : 17.0) * N);
+      CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, rows, -P->kx,
+                        P->dpen, 0, s, sub, theta));
+    }
+    return matvec_cols3(P, x, y, s);
+  }
   {
     ProfScope ps(P, s, kCatMvRows, (sub ? 25.0 : 17.0) * N);
     CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
@@ -420,8 +459,66 @@ int precond_chirp(Plan* P, const double* r, const double* sig, double* z, int t,
   return RSFDE_OK;
 }
 
+// Three-dimensional P_hat^{-1} (n + 1 a power of two on every axis), T internals:
+//   A:  Q  = raw x-sine sums of the rows of sig*v            (all n2*n3 rows)
+//   B1: R  = raw y-sine sums of Q's columns                   (per z slice)
+//   B2: P1, P2 = raw z-sine sums of K R / E1 and K R / E2     (columns of the
+//       [n3][(n1+1) n2] view; E1 = 1 - kx lx - ky ly - kz lz, E2 = E1 + dt/eta)
+//   B3: Q, R = raw y-sine sums of P1, P2                      (per z slice)
+//   C:  z  = mask (Q S_x) + (1 - mask) (R S_x), fused with the matrix-vector row
+//       pass when w is given (then followed by the y and z passes into w).
+// K = 8 / ((n1+1)(n2+1)(n3+1)) collects the orthonormal sine factors.
+template <typename T>
+int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<int, void*>& tw,
+             const T* lamc, const T* lamz, hipStream_t s, double* w, const double* sub,
+             double theta) {
+  const int n1 = P->n1, n2 = P->n2, n3 = P->n3, ld = n1 + 1, rows = n2 * n3;
+  const size_t plane = (size_t)ld * n2;
+  const double Kfac = 8.0 / ((double)(n1 + 1) * (double)(n2 + 1) * (double)(n3 + 1));
+  const double N = (double)P->N, S = (double)plane * n3, ts = (double)sizeof(T);
+  T *Q = (T*)P->Q, *R = (T*)P->R3, *P1 = (T*)P->P1, *P2 = (T*)P->P2;
+  {
+    ProfScope ps(P, s, kCatPcRows, 8.0 * N + ts * S);
+    CK(launch_pc_rows_fwd<T>(P->Ldx, r, sig, Q, tw[P->Ldx], n1, rows, s));
+  }
+  {
+    ProfScope ps(P, s, kCatDstCols, 2.0 * ts * S);
+    CK(launch_dst_cols<T>(P->Ldy, Q, Q, R, R, tw[P->Ldy], ld / 2, 2, 1, n2, ld, n3, plane, s));
+  }
+  {
+    ProfScope ps(P, s, kCatPcCols, 3.0 * ts * S);
+    CK(launch_pc_cols<T>(P->Ldz, R, P1, P2, lamc, lamz, tw[P->Ldz], (int)plane - 1, n3, 1.0, P->kz,
+                         P->dpen, Kfac, s));
+  }
+  {
+    ProfScope ps(P, s, kCatDstCols, 4.0 * ts * S);
+    CK(launch_dst_cols<T>(P->Ldy, P1, P2, Q, R, tw[P->Ldy], ld, 1, 0, n2, ld, n3, plane, s));
+  }
+  if (!w || P->Ldx != P->Lcx) {  // unfused (n1 = 1: convolution and sine lengths differ)
+    {
+      ProfScope ps(P, s, kCatPcRowsInv, 2.0 * ts * S + 9.0 * N);
+      CK(launch_pc_rows_inv<T>(P->Ldx, Q, R, P->mirror, P->mask, z, tw[P->Ldx], n1, rows, s));
+    }
+    return w ? matvec_impl(P, z, w, s, sub, theta) : RSFDE_OK;
+  }
+  {
+    ProfScope ps(P, s, kCatPcInvMv, 2.0 * ts * S + 17.0 * N + (sub ? 8.0 * N : 0.0));
+    CK(launch_pc_rows_inv_mv<T>(P->Ldx, Q, R, P->mirror, P->mask, z, P->t, tw[P->Ldx],
+                                P->tw64[P->Ldx], P->symx, -P->kx, P->dpen, sub, theta, n1, rows,
+                                s));
+  }
+  return matvec_cols3(P, z, w, s);
+}
+
 int precond_impl(Plan* P, const double* r, const double* sig, double* z, int precision,
                  hipStream_t s) {
+  if (P->is3d) {
+    if (precision == RSFDE_FP64)
+      return precond3<double>(P, r, sig, z, P->tw64, P->lamc64, P->lamz64, s, nullptr, nullptr, 0.0);
+    if (precision == RSFDE_FP32)
+      return precond3<float>(P, r, sig, z, P->tw32, P->lamc32, P->lamz32, s, nullptr, nullptr, 0.0);
+    return RSFDE_EUNSUPPORTED;
+  }
   if (precision == RSFDE_BF16) {
     ProfScope ps(P, s, kCatPcGemm, 17.0 * (double)P->N);
     CK(launch_pc_gemm_bf16(r, sig, z, P->mask, P->Sx16, P->Sy16, P->Sx16lo, P->Sy16lo, P->lamx_nat,
@@ -482,6 +579,13 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
 int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, double* w,
                         int precision, hipStream_t s, const double* sub = nullptr,
                         double theta = 0.0) {
+  if (P->is3d) {
+    if (precision == RSFDE_FP64)
+      return precond3<double>(P, v, sig, z, P->tw64, P->lamc64, P->lamz64, s, w, sub, theta);
+    if (precision == RSFDE_FP32)
+      return precond3<float>(P, v, sig, z, P->tw32, P->lamc32, P->lamz32, s, w, sub, theta);
+    return RSFDE_EUNSUPPORTED;
+  }
   const bool fused = P->Ldx && P->Ldy && P->Ldx == P->Lcx &&
                      (precision == RSFDE_FP64 || precision == RSFDE_FP32);
   if (!fused) {
@@ -536,6 +640,7 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
 
 int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (!o) return RSFDE_EINVAL;
+  if (P->is3d && o->precision == RSFDE_BF16) return RSFDE_EUNSUPPORTED;
   if (o->restart < 1 || o->restart > P->max_restart) return RSFDE_EINVAL;
   if (o->max_iters < 1) return RSFDE_EINVAL;
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RSFDE_EINVAL;
@@ -1037,6 +1142,104 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
 
 using rsfde::Plan;
 
+namespace rsfde {
+namespace {
+
+// Workspaces every plan needs: the mask copy, Krylov basis V (restart + 1
+// vectors) and Z (restart), five work vectors, three (four in 3-D)
+// preconditioner intermediates of `slots` values (sized for FP64), the 3-D
+// matrix-vector intermediate, reduction and s-step buffers, pinned status
+// words and events.  Enqueued on s.
+int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) {
+  const size_t N = P->N, ld = P->ldv;
+  const int max_restart = P->max_restart;
+#define AL(ptr, cnt)                                              \
+  do {                                                            \
+    if (P->dalloc(&(ptr), (cnt)) != hipSuccess) return RSFDE_ENOMEM; \
+  } while (0)
+  AL(P->mask, N);
+  AL(P->V, (size_t)(max_restart + 1) * ld);
+  AL(P->Z, (size_t)max_restart * ld);
+  AL(P->b, ld);
+  AL(P->w, ld);
+  AL(P->t, ld);
+  AL(P->mu, ld);
+  AL(P->pb, ld);
+  double* q = nullptr;
+  AL(q, slots);
+  P->Q = q;
+  AL(q, slots);
+  P->P1 = q;
+  AL(q, slots);
+  P->P2 = q;
+  if (P->is3d) {
+    AL(q, slots);
+    P->R3 = q;
+    AL(P->t3, ld);
+  }
+  AL(P->ks, 1);
+  AL(P->rw.partial, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
+  AL(P->gpart, (size_t)16 * 16 * kGramMaxTiles * kGramBlocks);
+  AL(P->coef_d, (size_t)16 * 16 * kGramMaxTiles + 256);
+#undef AL
+  if (hipHostMalloc((void**)&P->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return RSFDE_ENOMEM;
+  std::memset((void*)P->hs, 0, sizeof(HostStatus));
+  if (hipHostGetDevicePointer((void**)&P->hs_dev, P->hs, 0) != hipSuccess) return RSFDE_EHIP;
+  if (hipHostMalloc((void**)&P->gram_h, sizeof(double) * 16 * 16 * kGramMaxTiles,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc((void**)&P->coef_h, sizeof(double) * (16 * 16 * kGramMaxTiles + 256),
+                    hipHostMallocDefault) != hipSuccess)
+    return RSFDE_ENOMEM;
+  if (hipHostGetDevicePointer((void**)&P->gram_d, P->gram_h, 0) != hipSuccess) return RSFDE_EHIP;
+  for (auto& e : P->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return RSFDE_EHIP;
+
+  if (hipMemcpyAsync(P->mask, mask_dev, N, hipMemcpyDeviceToDevice, s) != hipSuccess) return RSFDE_EHIP;
+  if (hipMemsetAsync(P->ks, 0, sizeof(KrylovState), s) != hipSuccess) return RSFDE_EHIP;
+  return RSFDE_OK;
+}
+
+// Pass A/C tables of the power-of-two sine transform along x: eigenvalues in
+// slot order (0 at frequency 0) and the slot that mirrors each upper-half
+// register position (-1 where the spectrum is zero).
+void slot_tables(const std::vector<double>& lx, int Lx, std::vector<double>& lam,
+                 std::vector<int>& mirror) {
+  const int n1 = (int)lx.size(), Px = fft_pts(Lx);
+  lam.assign(n1 + 1, 0.0);
+  mirror.assign(Lx, -1);
+  std::vector<int> slot_of_f(Lx / 2, -1);
+  for (int c = 0; c < n1 + 1; ++c) {
+    const int f = fft_freq(Lx, Px, fft_slot_pos(Lx, Px, c));
+    lam[c] = (f >= 1 && f <= n1) ? lx[f - 1] : 0.0;
+    slot_of_f[f] = c;
+  }
+  for (int p = 0; p < Lx; ++p) {
+    const int f = fft_freq(Lx, Px, p);
+    if (f >= Lx / 2) {
+      const int g = Lx - f;
+      mirror[p] = (g == Lx / 2) ? -1 : slot_of_f[g];
+    }
+  }
+}
+
+// Column-pass eigenvalues in register-position order of the length-L FFT
+// (even in frequency; 0 at frequencies 0 and L/2).
+std::vector<double> pos_eigs(const std::vector<double>& ly, int L) {
+  const int n = (int)ly.size(), Py = pc_cols_pts(L);
+  std::vector<double> lam(L);
+  for (int p = 0; p < L; ++p) {
+    const int f = fft_freq(L, Py, p);
+    const int g = std::min(f, L - f);
+    lam[p] = (g >= 1 && g <= n) ? ly[g - 1] : 0.0;
+  }
+  return lam;
+}
+
+}  // namespace
+}  // namespace rsfde
+
 struct rsfde_plan_s {
   Plan p;
 };
@@ -1125,48 +1328,8 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     P->Lgy = std::max(2, next_pow2(2L * n2 - 1));
   }
 
-  const size_t N = P->N, ld = P->ldv;
   const size_t slots = (size_t)(n1 + 1) * (size_t)n2;
-#define AL(ptr, cnt)                                              \
-  do {                                                            \
-    if (P->dalloc(&(ptr), (cnt)) != hipSuccess) return fail(RSFDE_ENOMEM); \
-  } while (0)
-  AL(P->mask, N);
-  AL(P->V, (size_t)(max_restart + 1) * ld);
-  AL(P->Z, (size_t)max_restart * ld);
-  AL(P->b, ld);
-  AL(P->w, ld);
-  AL(P->t, ld);
-  AL(P->mu, ld);
-  AL(P->pb, ld);
-  double* q = nullptr;
-  AL(q, slots);
-  P->Q = q;
-  AL(q, slots);
-  P->P1 = q;
-  AL(q, slots);
-  P->P2 = q;
-  AL(P->ks, 1);
-  AL(P->rw.partial, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
-  AL(P->gpart, (size_t)16 * 16 * kGramMaxTiles * kGramBlocks);
-  AL(P->coef_d, (size_t)16 * 16 * kGramMaxTiles + 256);
-#undef AL
-  if (hipHostMalloc((void**)&P->hs, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
-      hipSuccess)
-    return fail(RSFDE_ENOMEM);
-  std::memset((void*)P->hs, 0, sizeof(HostStatus));
-  if (hipHostGetDevicePointer((void**)&P->hs_dev, P->hs, 0) != hipSuccess) return fail(RSFDE_EHIP);
-  if (hipHostMalloc((void**)&P->gram_h, sizeof(double) * 16 * 16 * kGramMaxTiles,
-                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-      hipHostMalloc((void**)&P->coef_h, sizeof(double) * (16 * 16 * kGramMaxTiles + 256),
-                    hipHostMallocDefault) != hipSuccess)
-    return fail(RSFDE_ENOMEM);
-  if (hipHostGetDevicePointer((void**)&P->gram_d, P->gram_h, 0) != hipSuccess) return fail(RSFDE_EHIP);
-  for (auto& e : P->ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RSFDE_EHIP);
-
-  if (hipMemcpyAsync(P->mask, mask_dev, N, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(RSFDE_EHIP);
-  if (hipMemsetAsync(P->ks, 0, sizeof(KrylovState), s) != hipSuccess) return fail(RSFDE_EHIP);
+  if ((rc = alloc_common(P, mask_dev, slots, s)) != RSFDE_OK) return fail(rc);
 
   // Matrix-vector symbols (unit kx, ky).
   if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return fail(RSFDE_ENOMEM);
@@ -1176,28 +1339,10 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
 
   // Preconditioner tables (Section 4.1), in the layouts of the three passes.
   if (P->Ldx && P->Ldy) {
-    const std::vector<double> lx = tau_eigs(tx), ly = tau_eigs(ty);
-    const int Lx = P->Ldx, Px = fft_pts(Lx);
-    const int Ly = P->Ldy, Py = pc_cols_pts(Ly);
-    std::vector<double> lamx(n1 + 1), lamy(Ly);
-    std::vector<int> slot_of_f(Lx / 2, -1), mirror(Lx, -1);
-    for (int c = 0; c < n1 + 1; ++c) {
-      const int f = fft_freq(Lx, Px, fft_slot_pos(Lx, Px, c));
-      lamx[c] = (f >= 1 && f <= n1) ? lx[f - 1] : 0.0;
-      slot_of_f[f] = c;
-    }
-    for (int p = 0; p < Lx; ++p) {
-      const int f = fft_freq(Lx, Px, p);
-      if (f >= Lx / 2) {
-        const int g = Lx - f;
-        mirror[p] = (g == Lx / 2) ? -1 : slot_of_f[g];
-      }
-    }
-    for (int p = 0; p < Ly; ++p) {
-      const int f = fft_freq(Ly, Py, p);
-      const int g = std::min(f, Ly - f);
-      lamy[p] = (g >= 1 && g <= n2) ? ly[g - 1] : 0.0;
-    }
+    std::vector<double> lamx;
+    std::vector<int> mirror;
+    slot_tables(tau_eigs(tx), P->Ldx, lamx, mirror);
+    const std::vector<double> lamy = pos_eigs(tau_eigs(ty), P->Ldy);
     std::vector<float> lamx_f(lamx.begin(), lamx.end()), lamy_f(lamy.begin(), lamy.end());
     if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
         upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess ||
@@ -1255,8 +1400,107 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   return RSFDE_OK;
 }
 
+int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double alpha2,
+                 double alpha3, double kx, double ky, double kz, const uint8_t* mask_dev,
+                 double eta, double dt, int32_t max_restart, void* stream) {
+  using namespace rsfde;
+  if (!out) return RSFDE_EINVAL;
+  *out = nullptr;
+  if (!grid || !mask_dev) return RSFDE_EINVAL;
+  const int n[3] = {grid->n1, grid->n2, grid->n3};
+  const double lo[3] = {grid->x_lo, grid->y_lo, grid->z_lo};
+  const double hi[3] = {grid->x_hi, grid->y_hi, grid->z_hi};
+  const double al[3] = {alpha1, alpha2, alpha3};
+  const double ks[3] = {kx, ky, kz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return RSFDE_EINVAL;
+    if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a])) return RSFDE_EINVAL;
+    if (!(al[a] > 1.0 && al[a] < 2.0)) return RSFDE_EINVAL;
+    if (!(ks[a] >= 0.0) || !std::isfinite(ks[a])) return RSFDE_EINVAL;
+  }
+  if (!(eta > 0.0) || !(dt > 0.0) || !std::isfinite(eta) || !std::isfinite(dt)) return RSFDE_EINVAL;
+  if (max_restart <= 0) max_restart = 30;
+  if (max_restart > kMaxRestart) return RSFDE_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (n[a] > kMaxN || !is_pow2(n[a] + 1)) return RSFDE_EUNSUPPORTED;
+  const size_t N = (size_t)n[0] * (size_t)n[1] * (size_t)n[2];
+  const size_t slots = (size_t)(n[0] + 1) * (size_t)n[1] * (size_t)n[2];
+  if (slots > (size_t)INT32_MAX) return RSFDE_EUNSUPPORTED;
+
+  rsfde_plan_s* h = new (std::nothrow) rsfde_plan_s();
+  if (!h) return RSFDE_ENOMEM;
+  Plan* P = &h->p;
+  auto fail = [&](int code) {
+    delete h;
+    return code;
+  };
+  if (hipGetDevice(&P->dev) != hipSuccess) return fail(RSFDE_EHIP);
+  hipStream_t s = (hipStream_t)stream;
+  P->s0 = s;
+  P->n1 = n[0];
+  P->n2 = n[1];
+  P->n3 = n[2];
+  P->is3d = true;
+  P->N = N;
+  P->ldv = (N + 63) / 64 * 64;
+  P->alpha1 = alpha1;
+  P->alpha2 = alpha2;
+  P->alpha3 = alpha3;
+  P->kx = kx;
+  P->ky = ky;
+  P->kz = kz;
+  P->eta = eta;
+  P->dt = dt;
+  P->dpen = dt / eta;
+  P->max_restart = max_restart;
+  {
+    const char* tr = std::getenv("RSFDE_TRACE");
+    P->trace = tr && tr[0] == '1';
+  }
+  // Section 2 on each axis: unit-k Toeplitz columns c = dt c_alpha / h^alpha.
+  std::vector<double> t[3];
+  for (int a = 0; a < 3; ++a) {
+    const double hstep = (hi[a] - lo[a]) / (n[a] + 1);
+    const double ca = -1.0 / (2.0 * std::cos(al[a] * kPi / 2.0));
+    t[a] = toeplitz_col(al[a], n[a], dt * ca / std::pow(hstep, al[a]));
+  }
+  P->Lcx = std::max(2, next_pow2(2L * n[0]));
+  P->Lcy = std::max(2, next_pow2(2L * n[1]));
+  P->Lcz = std::max(2, next_pow2(2L * n[2]));
+  P->Ldx = 2 * (n[0] + 1);
+  P->Ldy = 2 * (n[1] + 1);
+  P->Ldz = 2 * (n[2] + 1);
+  int rc = alloc_common(P, mask_dev, slots, s);
+  if (rc != RSFDE_OK) return fail(rc);
+  if (upload(P, &P->symx, conv_symbol_pos(t[0], P->Lcx), s) != hipSuccess ||
+      upload(P, &P->symy, conv_symbol_pos(t[1], P->Lcy), s) != hipSuccess ||
+      upload(P, &P->symz, conv_symbol_pos(t[2], P->Lcz), s) != hipSuccess)
+    return fail(RSFDE_ENOMEM);
+  for (int L : {P->Lcx, P->Lcy, P->Lcz, P->Ldx, P->Ldy, P->Ldz})
+    if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
+  // Section 4.1's eigenvalues: x in slot order folded with y into one value per
+  // column of the [n3][(n1+1) n2] view (k included), z in position order (unit kz).
+  std::vector<double> lamx;
+  std::vector<int> mirror;
+  slot_tables(tau_eigs(t[0]), P->Ldx, lamx, mirror);
+  const std::vector<double> ly = tau_eigs(t[1]);
+  std::vector<double> lamc((size_t)(n[0] + 1) * n[1]);
+  for (int j = 0; j < n[1]; ++j)
+    for (int c = 0; c < n[0] + 1; ++c) lamc[(size_t)j * (n[0] + 1) + c] = kx * lamx[c] + ky * ly[j];
+  const std::vector<double> lamz = pos_eigs(tau_eigs(t[2]), P->Ldz);
+  const std::vector<float> lamc_f(lamc.begin(), lamc.end()), lamz_f(lamz.begin(), lamz.end());
+  if (upload(P, &P->lamc64, lamc, s) != hipSuccess || upload(P, &P->lamc32, lamc_f, s) != hipSuccess ||
+      upload(P, &P->lamz64, lamz, s) != hipSuccess || upload(P, &P->lamz32, lamz_f, s) != hipSuccess ||
+      upload(P, &P->mirror, mirror, s) != hipSuccess)
+    return fail(RSFDE_ENOMEM);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(RSFDE_EHIP);
+  *out = h;
+  return RSFDE_OK;
+}
+
 int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky) {
   if (!plan) return RSFDE_EINVAL;
+  if (plan->p.is3d) return RSFDE_EUNSUPPORTED;
   if (!(kx >= 0.0) || !(ky >= 0.0) || !std::isfinite(kx) || !std::isfinite(ky)) return RSFDE_EINVAL;
   plan->p.kx = kx;
   plan->p.ky = ky;
@@ -1336,6 +1580,7 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
     return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   Plan* P = &plan->p;
+  if (P->is3d) return finish(stats, RSFDE_EUNSUPPORTED, 0, 0, 0, 0);
   int rc = validate_opts(P, opts);
   if (rc) return finish(stats, rc, 0, 0, 0, 0);
   DeviceGuard g(P->dev);

@@ -48,9 +48,36 @@ class RsfdePlan:
                    w.ky if ky is None else ky, mask, w.eta, w.T / w.m,
                    w.restart if max_restart is None else max_restart, device)
 
+    @classmethod
+    def setup3(cls, n, box, alphas, ks, mask, eta, dt, max_restart=30, device=None):
+        """A three-dimensional plan (rsfde_setup3): n = (n1, n2, n3), box of six
+        bounds, per-axis alphas and ks, mask [n3][n2][n1]."""
+        self = cls.__new__(cls)
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        if not isinstance(mask, torch.Tensor):
+            mask = torch.as_tensor(mask)
+        self.mask = mask.to(device=dev, dtype=torch.uint8).contiguous().reshape(-1)
+        self.n1, self.n2, self.n3 = (int(v) for v in n)
+        self.box = tuple(float(v) for v in box)
+        self.alpha1, self.alpha2, self.alpha3 = (float(a) for a in alphas)
+        self.kx, self.ky, self.kz = (float(k) for k in ks)
+        self.eta, self.dt = float(eta), float(dt)
+        self.device = dev
+        with torch.cuda.device(dev):
+            self.handle = L.rsfde_setup3(n, box, alphas, ks, self.mask, eta, dt, max_restart)
+        return self
+
+    @classmethod
+    def from_workload3(cls, w, max_restart=None, device=None):
+        return cls.setup3((w.n1, w.n2, w.n3), w.box, (w.alpha1, w.alpha2, w.alpha3),
+                          (w.kx, w.ky, w.kz), torch.as_tensor(w.mask), w.eta, w.T / w.m,
+                          w.restart if max_restart is None else max_restart, device)
+
+    n3 = 1  # two-dimensional unless set by setup3
+
     @property
     def N(self):
-        return self.n1 * self.n2
+        return self.n1 * self.n2 * self.n3
 
     def close(self):
         if getattr(self, "handle", None) is not None:
