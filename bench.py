@@ -53,6 +53,38 @@ def fft_flops(family, n1, n2):
         "pc_inv_mv_rows": n2 * f(Ldx) + ((n2 + 1) // 2) * 2 * f(Lcx),
     }
     return table.get(family)
+
+
+def fft_flops3(family, n1, n2, n3):
+    """As fft_flops for the three-dimensional plan: (flops of one operator
+    application's launches of `family`, launches per application).  mv_cols is
+    the y pass (per z slice) plus the z pass; dst_cols the stand-alone y
+    transforms before and after the z pass of the preconditioner."""
+    import math
+
+    def f(L):
+        return 5.0 * L * math.log2(L)
+
+    def p2(v):
+        L = 1
+        while L < v:
+            L *= 2
+        return L
+    Lc = [max(2, p2(2 * n)) for n in (n1, n2, n3)]
+    Ld = [2 * (n + 1) for n in (n1, n2, n3)]
+    rows, ld = n2 * n3, n1 + 1
+    table = {
+        "mv_rows": (((rows + 1) // 2) * 2 * f(Lc[0]), 1),
+        "mv_cols": (((n1 + 1) // 2) * n3 * 2 * f(Lc[1]) + ((n1 * n2 + 1) // 2) * 2 * f(Lc[2]), 2),
+        "pc_rows_fwd": (((rows + 1) // 2) * f(Ld[0]), 1),
+        "dst_cols": ((ld // 2) * n3 * f(Ld[1]) + ld * n3 * f(Ld[1]), 2),
+        "pc_cols": ((ld * n2 // 2) * 3 * f(Ld[2]), 1),
+        "pc_rows_inv": (rows * f(Ld[0]), 1),
+        "pc_inv_mv_rows": (rows * f(Ld[0]) + ((rows + 1) // 2) * 2 * f(Lc[0]), 1),
+    }
+    return table.get(family)
+
+
 METRIC = "unknown·timesteps/s at 2047², mixed vs FP64 at 1e-8 rel err; adjoint grads/s"
 
 
@@ -67,7 +99,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--mode", choices=["march", "kernels", "ablations"], default="march",
+    ap.add_argument("--no-three-d", action="store_true")
+    ap.add_argument("--mode", choices=["march", "kernels", "ablations", "three_d"], default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-ensemble", action="store_true")
@@ -255,6 +288,74 @@ def ensemble_rate(log, sstep=0, members=8, steps=8):
             "speedup": t_seq / t_conc}
 
 
+def three_d_rate(log, sstep=8, steps=4, profile=True, one_vector=True, fp32=True):
+    """The three-dimensional plan on its 255^3 workload (ellipsoid, alpha =
+    (1.6, 1.7, 1.8), 16 steps to T = 1, f = u(1-u), GMRES(30) tol 1e-8): the
+    first `steps` implicit steps after one warm-up step, s-step and one-vector
+    GMRES with the FP64 preconditioner and s-step with FP32 internals, plus the
+    per-family kernel times of the s-step run (HIP events)."""
+    import numpy as np
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from paper_2102_11576_amd import _lib as L
+    from workloads.three_d import make_config3d
+    w = make_config3d()
+    dev = torch.device("cuda:0")
+    res = {"workload": (f"e3: {w.n1}x{w.n2}x{w.n3} grid, ellipsoid 0.45/0.35/0.30 in [0,1]^3, "
+                        f"alpha=({w.alpha1},{w.alpha2},{w.alpha3}), k=(1,1,1), eta={w.eta}, "
+                        f"{w.m} steps to T={w.T}, f=u(1-u), 6 seeded Gaussian bumps, "
+                        f"FGMRES({w.restart}) tol {w.tol}; first {steps} steps timed"),
+           "unit": "unknown·timesteps/s", "N": w.N}
+    with RsfdePlan.from_workload3(w, device=dev) as pl:
+        u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+
+        def run(precision, ss, prof=False):
+            opts = make_opts(w.restart, 100000, w.tol, precision, sstep=ss)
+            pl.march(u0, 1, w.f_kind, opts)
+            torch.cuda.synchronize()
+            if prof:
+                L.rsfde_profile(pl.handle, True)
+                L.rsfde_profile_read(pl.handle)
+            t0 = time.perf_counter()
+            u, it, _ = pl.march(u0, steps, w.f_kind, opts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            pr = None
+            if prof:
+                pr = L.rsfde_profile_read(pl.handle)
+                L.rsfde_profile(pl.handle, False)
+            form = f"s-step (s={ss})" if ss >= 2 else "one vector per step"
+            log(f"3-D {precision}, {form}: {1e3 * dt / steps:.2f} ms/step, "
+                f"{np.mean(it):.1f} iterations/step")
+            return u, {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                       "gmres_iters_per_step": float(np.mean(it)), "gmres_form": form,
+                       "preconditioner": precision}, pr
+
+        u8, main, _ = run("fp64", sstep)
+        res.update(main)
+        if one_vector:
+            u1, one, _ = run("fp64", 0)
+            one["rel_err_inf_vs_sstep"] = float((u1 - u8).abs().max() / u8.abs().max())
+            res["one_vector_per_step"] = one
+        if fp32:
+            u32, r32, _ = run("fp32", sstep)
+            r32["rel_err_inf_vs_fp64"] = float((u32 - u8).abs().max() / u8.abs().max())
+            res["fp32"] = r32
+        if profile:
+            _, _, pr = run("fp64", sstep, prof=True)
+            kernels = {}
+            for name, (n, ms, by) in sorted(pr.items(), key=lambda kv: -kv[1][1]):
+                kv = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n,
+                      "alg_GBs": by / (ms * 1e-3) / 1e9 if ms > 0 else None}
+                fl = fft_flops3(name, w.n1, w.n2, w.n3)
+                if fl is not None and ms > 0:
+                    kv["fp64_TFs"] = fl[0] * (n / fl[1]) / (ms * 1e-3) / 1e12
+                    kv["frac_of_fp64_valu_peak"] = kv["fp64_TFs"] / FP64_VALU_PEAK_TFS
+                kernels[name] = kv
+            res["kernels"] = kernels
+    return res
+
+
 def traffic_for(kernel, bytes_per_launch):
     """Measured HBM bytes per launch of `kernel` from the committed counter
     summary, if it was taken on the current kernel sources (else None)."""
@@ -318,6 +419,12 @@ def main():
         return
     if args.mode == "ablations":
         ablations(args)
+        return
+    if args.mode == "three_d":  # the 3-D leg alone (for kernel traces)
+        print(json.dumps({"three_d": three_d_rate(log, args.sstep, args.steps or 4,
+                                                  profile=not args.no_profile,
+                                                  one_vector=not args.no_one_vector,
+                                                  fp32=not args.no_mixed)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the grid "
@@ -466,6 +573,9 @@ def main():
 
     if not args.no_ensemble:
         out["ensemble"] = ensemble_rate(log, args.sstep)
+
+    if not args.no_three_d:
+        out["three_d"] = three_d_rate(log, args.sstep)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")

@@ -39,6 +39,7 @@ FAMILIES = [
     (r"k_pc_cols<", "pc_cols"),
     (r"k_pc_rows_inv<", "pc_rows_inv"),
     (r"k_pc_rows_inv_mv<", "pc_inv_mv_rows"),
+    (r"k_dst_cols<", "dst_cols"),
     (r"k_gemm_bf16", "pc_gemm_bf16"),
     (r"k_residual\b", "residual"),
     (r"k_rhs\b", "rhs"),
@@ -79,7 +80,7 @@ def family(name: str) -> str:
         if re.search(pat, name):
             suffix = ""
             m = re.search(r"<(double|float)", name)
-            if m and (fam.startswith("pc_") or fam.startswith("cd_")):
+            if m and (fam.startswith("pc_") or fam.startswith("cd_") or fam == "dst_cols"):
                 suffix = "<" + m.group(1) + ">"
             return fam + suffix
     return "other"
