@@ -26,7 +26,7 @@ struct HostStatus {
   double beta;              // ||r|| of the last residual kernel
   double bnorm;             // ||b||
   int32_t flags;            // bit 0: non-finite value seen
-  int32_t pad;
+  int32_t gram_seq;         // sequence number of the last Gram block written (s-step form)
 };
 constexpr int kFlagNonFinite = 1;
 
@@ -151,19 +151,31 @@ hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double*
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
                          KrylovState* ks, bool scaled, hipStream_t s);
 // x += sum_{i<jc} c_i Z_i with the coefficients c given (device array).
+// As launch_update with the coefficients y given on the host (jc doubles,
+// passed to the kernels as arguments).
 hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                              const double* c, hipStream_t s);
+                              const double* c_host, hipStream_t s);
 
 // s-step blocks (krylov_block.hip).  G (pinned, device-visible, [nr][16]) =
 // [V_0 .. V_{nr-1}]^T [V_{m1} .. V_{m1+s-1}]; gpart holds
 // 16 * 16 * kGramMaxTiles * kGramBlocks partial sums.
 constexpr int kGramBlocks = 1024;
 constexpr int kGramMaxTiles = 5;  // up to 80 Gram rows
+// After G is written and fenced, the finishing kernel stores seq to *seq_flag
+// (pinned host memory), so that the host can wait for G by polling that word.
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
-                        double* gpart, double* G_host_dev, hipStream_t st);
-// V_{m1..m1+s-1} <- (V_{m1..} - V_{0..nq-1} C) R^{-1}; coef = C [nq][s] then R^{-1} [s][s].
+                        double* gpart, double* G_host_dev, int32_t* seq_flag, int32_t seq,
+                        hipStream_t st);
+// V_{m1..m1+s-1} <- (V_{m1..} - V_{0..nq-1} C) R^{-1}; coef = C [nq][s] then R^{-1} [s][s]
+// (nq*s + s*s doubles).  Up to kCoefArgMax coefficients travel as kernel
+// arguments (coef is then a host pointer); more are read from coef_dev, which
+// the caller has filled on the stream.
+constexpr int kCoefArgMax = 448;
+struct CoefArgs {
+  double v[kCoefArgMax];
+};
 hipError_t launch_bupd(double* V, size_t ld, int nq, int m1, int s, size_t N, const double* coef,
-                       hipStream_t st);
+                       const double* coef_dev, hipStream_t st);
 hipError_t launch_scale_copy(const double* v, const double* sig, double* z, size_t N,
                              hipStream_t s);
 hipError_t launch_adj_lambda(const double* mu, const double* u_prev, const uint8_t* mask,

@@ -103,9 +103,11 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 
 // G[r * 16 + c] = sum of the partials (fixed order), written where the host
 // reads it (pinned, device-visible memory).
+// Then every writer fences at system scope, and thread 0 publishes seq.
 __global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* __restrict__ gpart,
                                                                  int nr, int s, int nb,
-                                                                 double* G) {
+                                                                 double* G, int32_t* seq_flag,
+                                                                 int32_t seq) {
   const int lane = threadIdx.x & 63;
   for (int p = threadIdx.x >> 6; p < nr * s; p += kFinishThreads / 64) {
     const int r = p / s, c = p % s;
@@ -115,17 +117,23 @@ __global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* _
     x = wave_sum(x);
     if (lane == 0) G[r * 16 + c] = x;
   }
+  __threadfence_system();
   __syncthreads();
-  if (threadIdx.x == 0) __threadfence_system();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile int32_t*>(seq_flag) = seq;
+  }
 }
 
 // U <- (U - Q C) R^{-1} in place, U = V + m1*ld (S vectors), Q = V (nq vectors).
 // coef: C row-major [nq][S] followed by R^{-1} row-major [S][S] (upper
 // triangular); uniform reads, so they come through the scalar cache.
-template <int S>
+template <int S, bool ARGS>
 __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, size_t ld, int nq,
                                                       int m1, size_t N,
-                                                      const double* __restrict__ coef) {
+                                                      const double* __restrict__ coef_dev,
+                                                      const CoefArgs args) {
+  const double* __restrict__ coef = ARGS ? args.v : coef_dev;
   const double* __restrict__ Rinv = coef + (size_t)nq * S;
   double* U = V + (size_t)m1 * ld;
   const size_t N2 = N / 2;
@@ -192,7 +200,8 @@ __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, si
 // ------------------------------- launchers --------------------------------
 
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
-                        double* gpart, double* G_host_dev, hipStream_t st) {
+                        double* gpart, double* G_host_dev, int32_t* seq_flag, int32_t seq,
+                        hipStream_t st) {
   if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
   int nb = (int)((N / 32 + 4 * 4 - 1) / (4 * 4));  // >= 4 chunks per wave
   if (nb < 1) nb = 1;
@@ -207,16 +216,29 @@ hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(k_bgram_finish, dim3(1), dim3(kFinishThreads), 0, st, gpart, nr, s, nb,
-                     G_host_dev);
+                     G_host_dev, seq_flag, seq);
   return hipGetLastError();
 }
 
 hipError_t launch_bupd(double* V, size_t ld, int nq, int m1, int s, size_t N, const double* coef,
-                       hipStream_t st) {
+                       const double* coef_dev, hipStream_t st) {
   const dim3 g(red_blocks(N)), b(kRedThreads);
+  const size_t nc = (size_t)nq * s + (size_t)s * s;
+  const bool by_args = nc <= (size_t)kCoefArgMax;
+  CoefArgs a;
+  if (by_args) {
+    for (size_t i = 0; i < nc; ++i) a.v[i] = coef[i];
+  } else if (!coef_dev) {
+    return hipErrorInvalidValue;
+  }
   switch (s) {
-#define X(SS) \
-  case SS: hipLaunchKernelGGL(k_bupd<SS>, g, b, 0, st, V, ld, nq, m1, N, coef); break;
+#define X(SS)                                                                                \
+  case SS:                                                                                   \
+    if (by_args)                                                                             \
+      hipLaunchKernelGGL((k_bupd<SS, true>), g, b, 0, st, V, ld, nq, m1, N, nullptr, a);     \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_bupd<SS, false>), g, b, 0, st, V, ld, nq, m1, N, coef_dev, a);   \
+    break;
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     default: return hipErrorInvalidValue;

@@ -8,15 +8,20 @@
 
 namespace rsfde {
 
+// Coefficients given by the host, passed as a kernel argument.
+struct UpdateCoef {
+  double v[kMaxRestart];
+};
+
 template <int NV>
 __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict__ Z, size_t ldz,
                                                         double* __restrict__ x, size_t N,
                                                         const KrylovState* __restrict__ ks,
-                                                        int v0, int jc, bool scaled,
-                                                        const double* __restrict__ cgiven) {
+                                                        int v0, int jc, bool scaled, bool given,
+                                                        const UpdateCoef cgiven) {
   __shared__ double y[kMaxRestart];
-  if (cgiven) {
-    if (threadIdx.x < NV) y[v0 + threadIdx.x] = cgiven[v0 + threadIdx.x];
+  if (given) {
+    if (threadIdx.x < NV) y[v0 + threadIdx.x] = cgiven.v[v0 + threadIdx.x];
   } else if (threadIdx.x == 0) {
     for (int i = jc - 1; i >= 0; --i) {
       double s = ks->g[i];
@@ -28,7 +33,7 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
   __syncthreads();
   double c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v] * (scaled && !cgiven ? ks->vscale[v0 + v] : 1.0);
+  for (int v = 0; v < NV; ++v) c[v] = y[v0 + v] * (scaled && !given ? ks->vscale[v0 + v] : 1.0);
   const size_t N2 = N / 2;
   double2* x2 = reinterpret_cast<double2*>(x);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N2;
@@ -53,12 +58,13 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
 }
 
 using UpdateFn = void (*)(const double*, size_t, double*, size_t, const KrylovState*, int, int,
-                          bool, const double*, dim3, hipStream_t);
+                          bool, bool, const UpdateCoef&, dim3, hipStream_t);
 template <int NV>
 static void run_update(const double* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
-                       int v0, int jc, bool scaled, const double* cg, dim3 g, hipStream_t s) {
+                       int v0, int jc, bool scaled, bool given, const UpdateCoef& cg, dim3 g,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc, scaled,
-                     cg);
+                     given, cg);
 }
 template <int... I>
 static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
@@ -70,9 +76,10 @@ hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t 
                          KrylovState* ks, bool scaled, hipStream_t s) {
   if (jc <= 0) return hipSuccess;
   if (jc > kMaxRestart) return hipErrorInvalidValue;
+  const UpdateCoef none{};
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, nullptr,
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, false, none,
                    dim3(red_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -81,12 +88,14 @@ hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t 
 }
 
 hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                              const double* c, hipStream_t s) {
+                              const double* c_host, hipStream_t s) {
   if (jc <= 0) return hipSuccess;
   if (jc > kMaxRestart) return hipErrorInvalidValue;
+  UpdateCoef cg{};
+  for (int i = 0; i < jc; ++i) cg.v[i] = c_host[i];
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, nullptr, v0, jc, false, c,
+    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, nullptr, v0, jc, false, true, cg,
                    dim3(red_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

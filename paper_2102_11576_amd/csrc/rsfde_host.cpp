@@ -137,6 +137,7 @@ struct Plan {
   double* gram_d = nullptr;
   double* coef_d = nullptr;
   double* coef_h = nullptr;
+  int32_t gram_seq = 0;  // last sequence number handed to a Gram block
   HostStatus* hs = nullptr;      // pinned host memory
   HostStatus* hs_dev = nullptr;  // its device-visible address
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -896,6 +897,43 @@ std::vector<double> lead_cols(const std::vector<double>& A, int rows, int n, int
 
 int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s);
 
+// Enqueues the Gram block of the s-step form and waits for it by polling the
+// sequence word its finishing kernel publishes in pinned memory (this wakes
+// sooner than a stream synchronisation); stops early if the stream drains or
+// fails without publishing.
+int gram_block(Plan* P, int nr, int nq, int ss, hipStream_t s) {
+  const int32_t seq = ++P->gram_seq;
+  {
+    ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)P->N);
+    CK(launch_bgram(P->V, P->ldv, nr, nq, ss, P->N, P->gpart, P->gram_d, &P->hs_dev->gram_seq,
+                    seq, s));
+  }
+  for (unsigned it = 1;; ++it) {
+    if (vread(&P->hs->gram_seq) == seq) return RSFDE_OK;
+    if ((it & 255) == 0) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) return vread(&P->hs->gram_seq) == seq ? RSFDE_OK : RSFDE_EHIP;
+      if (q != hipErrorNotReady) return RSFDE_EHIP;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// Enqueues U <- (U - Q C) R^{-1} with coef = C [nq][ss] then R^{-1} [ss][ss]
+// (host).  Small tables travel as kernel arguments; larger ones go through
+// the pinned staging buffer, which no earlier copy can still be reading: every
+// earlier copy precedes a Gram block the host has already waited for.
+int block_update(Plan* P, int nq, int ss, const double* coef, hipStream_t s) {
+  const size_t nc = (size_t)nq * ss + (size_t)ss * ss;
+  if (nc > (size_t)kCoefArgMax) {
+    std::copy(coef, coef + nc, P->coef_h);
+    CK(hipMemcpyAsync(P->coef_d, P->coef_h, nc * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  ProfScope ps(P, s, kCatBupd, 8.0 * (double)(nq + 2 * ss) * (double)P->N);
+  CK(launch_bupd(P->V, P->ldv, nq, nq, ss, P->N, coef, P->coef_d, s));
+  return RSFDE_OK;
+}
+
 // finish() that also reports the count of reorthogonalised / truncated blocks
 int finish_ev(rsfde_stats* st, int events, int code, int iters, int restarts, double beta,
               double bnorm) {
@@ -960,11 +998,8 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
       }
       const int nq = m + 1;
       int nr = m + 1 + ss;
-      {
-        ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)N);
-        CK(launch_bgram(P->V, ld, nr, nq, ss, N, P->gpart, P->gram_d, s));
-      }
-      CK(hipStreamSynchronize(s));
+      rc = gram_block(P, nr, nq, ss, s);
+      if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
       const double* G = P->gram_h;
       for (int i = 0; i < nr * 16; ++i)
         if (!std::isfinite(G[i])) return finish_ev(st, events, RSFDE_ENONFINITE, total, cycles, beta, bnorm);
@@ -985,18 +1020,10 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
         std::vector<double> coef((size_t)nq * ss + (size_t)ss * ss, 0.0);
         std::copy(C.begin(), C.end(), coef.begin());
         for (int k = 0; k < ss; ++k) coef[(size_t)nq * ss + k * ss + k] = 1.0;
-        std::copy(coef.begin(), coef.end(), P->coef_h);
-        CK(hipMemcpyAsync(P->coef_d, P->coef_h, coef.size() * sizeof(double),
-                          hipMemcpyHostToDevice, s));
-        {
-          ProfScope ps(P, s, kCatBupd, 8.0 * (double)(nq + 2 * ss) * (double)N);
-          CK(launch_bupd(P->V, ld, nq, nq, ss, N, P->coef_d, s));
-        }
-        {
-          ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)N);
-          CK(launch_bgram(P->V, ld, nr, nq, ss, N, P->gpart, P->gram_d, s));
-        }
-        CK(hipStreamSynchronize(s));
+        rc = block_update(P, nq, ss, coef.data(), s);
+        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
+        rc = gram_block(P, nr, nq, ss, s);
+        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
         kp = block_factor(P->gram_h, nq, ss, C2, R2);
         if (P->trace) {
           std::fprintf(stderr, "[rsfde s-step]   second pass pivots %d  diag(U'^T U')", kp);
@@ -1103,13 +1130,11 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
       }
       if (jc > 0) break;
       if (m + ss < jmax) {  // the block becomes orthonormal basis vectors
-        const size_t nc = (size_t)nq * ss + (size_t)ss * ss;
         const std::vector<double> Ri = upper_inverse(R, ss);
-        std::copy(Capply.begin(), Capply.end(), P->coef_h);
-        std::copy(Ri.begin(), Ri.end(), P->coef_h + (size_t)nq * ss);
-        CK(hipMemcpyAsync(P->coef_d, P->coef_h, nc * sizeof(double), hipMemcpyHostToDevice, s));
-        ProfScope ps(P, s, kCatBupd, 8.0 * (double)(nq + 2 * ss) * (double)N);
-        CK(launch_bupd(P->V, ld, nq, nq, ss, N, P->coef_d, s));
+        std::vector<double> coef(Capply);
+        coef.insert(coef.end(), Ri.begin(), Ri.end());
+        rc = block_update(P, nq, ss, coef.data(), s);
+        if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
       }
       m += ss;
     }
@@ -1122,16 +1147,15 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
       const double d = Hrot[(size_t)i * RS + i];
       y[i] = d != 0.0 ? v / d : 0.0;
     }
-    CK(hipStreamSynchronize(s));  // the staging buffer may still feed an update copy
+    std::vector<double> cz(jc);
     for (int i = 0; i < jc; ++i) {
       double v = 0.0;
       for (int l = i; l < jc; ++l) v += W[(size_t)i * RS + l] * y[l];
-      P->coef_h[i] = v;
+      cz[i] = v;
     }
-    CK(hipMemcpyAsync(P->coef_d, P->coef_h, (size_t)jc * sizeof(double), hipMemcpyHostToDevice, s));
     {
       ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
-      CK(launch_update_coef(P->Z, ld, jc, x, N, P->coef_d, s));
+      CK(launch_update_coef(P->Z, ld, jc, x, N, cz.data(), s));
     }
     total += jc;
   }
