@@ -46,6 +46,25 @@ def test_sstep_matches_lu(c4_71, s):
     assert np.abs(u - ref).max() / np.abs(ref).max() <= 1e-10
 
 
+@pytest.mark.parametrize("s,restart,reach", [(8, 60, 56), (16, 30, 32), (16, 48, 32)])
+def test_sstep_large_coefficient_tables_match_lu(s, restart, reach):
+    """Block updates whose coefficient table (nq*s + s*s doubles) outgrows the
+    kernel-argument limit (448) go through the staged copy: the first such
+    block starts at m = 48 for s = 8 and at m = 16 for s = 16, so a cycle
+    longer than `reach` iterations updates one.  Earlier blocks pass theirs as
+    arguments, so both paths run.  The c3 shape at 71^2 needs 63-88
+    iterations per step at tol 1e-12 (oracle GMRES)."""
+    w = make_config("c3", n=71, m=3)
+    p = O.problem_from_workload(w)
+    ref = O.march_lu(p, w.u0, w.m, w.f_kind)
+    with RsfdePlan.from_workload(w, max_restart=64) as pl:
+        u, its, _ = pl.march(_t(w.u0), w.m, w.f_kind,
+                             make_opts(restart, 100000, 1e-12, sstep=s))
+        u = u.cpu().numpy().reshape(w.n2, w.n1)
+    assert min(its) > reach, its
+    assert np.abs(u - ref).max() / np.abs(ref).max() <= 1e-10
+
+
 @pytest.mark.parametrize("s,restart,precision", [(5, 30, "fp64"), (3, 7, "fp64"), (4, 30, "fp32"),
                                                  (5, 12, "fp64")])
 def test_sstep_iterations_match_one_vector_form(s, restart, precision):
