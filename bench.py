@@ -106,7 +106,7 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-vector", action="store_true",
                     help="skip the one-vector-per-step comparison march (profiling runs)")
-    ap.add_argument("--sstep", type=int, default=8,
+    ap.add_argument("--sstep", type=int, default=10,
                     help="GMRES form of the timed march: s >= 2 the s-step block form, "
                          "0 one Arnoldi vector per step (both are reported)")
     return ap.parse_args()
@@ -288,7 +288,7 @@ def ensemble_rate(log, sstep=0, members=8, steps=8):
             "speedup": t_seq / t_conc}
 
 
-def three_d_rate(log, sstep=8, steps=4, profile=True, one_vector=True, fp32=True):
+def three_d_rate(log, sstep=10, steps=4, profile=True, one_vector=True, fp32=True):
     """The three-dimensional plan on its 255^3 workload (ellipsoid, alpha =
     (1.6, 1.7, 1.8), 16 steps to T = 1, f = u(1-u), GMRES(30) tol 1e-8): the
     first `steps` implicit steps after one warm-up step, s-step and one-vector
