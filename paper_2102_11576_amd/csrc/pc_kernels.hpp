@@ -55,6 +55,19 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
   const bool va = ra < n2, vb = rb < n2;
   const double* xa = v + (size_t)ra * n1;
   const double* xb = v + (size_t)rb * n1;
+  T* my = lds + b * lds_len(L);
+  // Stage both rows in this FFT's LDS region (row a at 0, row b at L/2) with
+  // contiguous loads: each value is fetched once, although the odd extension
+  // uses it twice.  n1 = L/2 - 1 < TPF * PP/2.
+  static_for<F::PP / 2>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int j = tau + k * F::TPF;
+    if (j < n1) {
+      my[j] = va ? (T)xa[j] : (T)0;
+      my[L / 2 + j] = vb ? (T)xb[j] : (T)0;
+    }
+  });
+  __syncthreads();
   cpx<T> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -68,21 +81,31 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
       idx = L - p - 1;
       sgn = (T)-1;
     }
-    reg[e].re = (va && idx >= 0) ? sgn * (T)xa[idx] : (T)0;
-    reg[e].im = (vb && idx >= 0) ? sgn * (T)xb[idx] : (T)0;
+    reg[e].re = idx >= 0 ? sgn * my[idx] : (T)0;
+    reg[e].im = idx >= 0 ? sgn * my[L / 2 + idx] : (T)0;
   });
-  T* my = lds + b * lds_len(L);
+  __syncthreads();  // the forward sweep reuses the region
   fft_forward<T, F>(reg, tau, tw, my);
   const T s = (T)(0.5 * (sig ? *sig : 1.0));
   const int ld = n1 + 1;
+  // Slots go through the LDS region (row a at 0, row b at ld = L/2) so that
+  // the global stores are contiguous across the wavefront.
+  __syncthreads();
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     constexpr int R = F::radix(F::NS - 1);
     if constexpr ((e % R) < R / 2) {
       const int slot = (tau + (e / R) * F::TPF) * (R / 2) + (e % R);
-      if (va) Q[(size_t)ra * ld + slot] = -reg[e].im * s;  // sigma_a
-      if (vb) Q[(size_t)rb * ld + slot] = reg[e].re * s;   // sigma_b
+      my[slot] = -reg[e].im * s;    // sigma_a
+      my[ld + slot] = reg[e].re * s;  // sigma_b
     }
+  });
+  __syncthreads();
+  static_for<F::PP / 2>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int j = tau + k * F::TPF;  // < L/2 = ld
+    if (va) Q[(size_t)ra * ld + j] = my[j];
+    if (vb) Q[(size_t)rb * ld + j] = my[ld + j];
   });
 }
 
@@ -231,6 +254,42 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_dst_cols(
   });
 }
 
+// Pass C's loads: one row of P1 and of P2 (ld = L/2 slots each) staged in an
+// FFT's LDS region with contiguous loads (P1 at 0, P2 at ld), then barrier.
+template <typename T, class F>
+__device__ __forceinline__ void stage_slots(const T* p1, const T* p2, bool vr, int ld, int tau,
+                                            T* my) {
+  static_for<F::PP / 2>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int j = tau + k * F::TPF;  // < L/2 = ld
+    my[j] = vr ? p1[j] : (T)0;
+    my[ld + j] = vr ? p2[j] : (T)0;
+  });
+  __syncthreads();
+}
+
+// The inverse sweep's input from the staged slots: P2/2 - i P1/2 on the lower
+// half of the spectrum, the odd mirror (table `mirror`) on the upper half; a
+// barrier follows, since the sweep reuses the region.
+template <typename T, class F>
+__device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, const int* __restrict__ mirror,
+                                                     int tau, int ld, T* my) {
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    constexpr int R = F::radix(F::NS - 1);
+    if constexpr ((e % R) < R / 2) {
+      const int slot = (tau + (e / R) * F::TPF) * (R / 2) + (e % R);
+      reg[e].re = (T)0.5 * my[ld + slot];
+      reg[e].im = (T)-0.5 * my[slot];
+    } else {
+      const int ms = mirror[F::pos(F::NS - 1, tau, e)];
+      reg[e].re = ms >= 0 ? (T)-0.5 * my[ld + ms] : (T)0;
+      reg[e].im = ms >= 0 ? (T)0.5 * my[ms] : (T)0;
+    }
+  });
+  __syncthreads();
+}
+
 // --------------------------------------------------------------------------
 // Pass C: one row r per FFT; spectrum P2/2 - i P1/2 on the lower half, odd
 // mirror on the upper half; the inverse sweep gives (P1 S_x) + i (P2 S_x).
@@ -250,22 +309,10 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
   const int ld = n1 + 1;
   const T* p1 = P1 + (size_t)r * ld;
   const T* p2 = P2 + (size_t)r * ld;
-  cpx<T> reg[F::PP];
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    constexpr int R = F::radix(F::NS - 1);
-    if constexpr ((e % R) < R / 2) {
-      const int slot = (tau + (e / R) * F::TPF) * (R / 2) + (e % R);
-      reg[e].re = vr ? (T)0.5 * p2[slot] : (T)0;
-      reg[e].im = vr ? (T)-0.5 * p1[slot] : (T)0;
-    } else {
-      const int ms = mirror[F::pos(F::NS - 1, tau, e)];
-      const bool ok = vr && ms >= 0;
-      reg[e].re = ok ? (T)-0.5 * p2[ms] : (T)0;
-      reg[e].im = ok ? (T)0.5 * p1[ms] : (T)0;
-    }
-  });
   T* my = lds + b * lds_len(L);
+  stage_slots<T, F>(p1, p2, vr, ld, tau, my);
+  cpx<T> reg[F::PP];
+  load_staged_spectrum<T, F>(reg, mirror, tau, ld, my);
   fft_inverse<T, F>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -321,22 +368,12 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     const bool vr = r < n2;
     const T* p1 = P1h + (size_t)r * ld;
     const T* p2 = P2h + (size_t)r * ld;
+    T* myT = reinterpret_cast<T*>(my);
+    __syncthreads();  // the previous row's sweep may still read the region
+    stage_slots<T, F>(p1, p2, vr, ld, th, myT);
     cpx<T> reg[F::PP];
-    static_for<F::PP>([&](auto ee) {
-      constexpr int e = decltype(ee)::value;
-      constexpr int R = F::radix(F::NS - 1);
-      if constexpr ((e % R) < R / 2) {
-        const int slot = (th + (e / R) * F::TPF) * (R / 2) + (e % R);
-        reg[e].re = vr ? (T)0.5 * p2[slot] : (T)0;
-        reg[e].im = vr ? (T)-0.5 * p1[slot] : (T)0;
-      } else {
-        const int ms = mih[F::pos(F::NS - 1, th, e)];
-        const bool ok = vr && ms >= 0;
-        reg[e].re = ok ? (T)-0.5 * p2[ms] : (T)0;
-        reg[e].im = ok ? (T)0.5 * p1[ms] : (T)0;
-      }
-    });
-    fft_inverse<T, F>(reg, th, twh, reinterpret_cast<T*>(my));
+    load_staged_spectrum<T, F>(reg, mih, th, ld, myT);
+    fft_inverse<T, F>(reg, th, twh, myT);
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int p = F::pos(0, th, e);
