@@ -195,6 +195,23 @@ RS_HD int fft_slot_pos(int L, int P, int c) {
   return (c / h) * R + (c % h);
 }
 
+// Slot holding frequency L - freq(p), for a position p of the upper half of
+// the spectrum (freq(p) >= L/2); -1 where that frequency is L/2.  Inverts the
+// digit reversal of fft_freq and then fft_slot_pos.
+RS_HD int fft_mirror_slot(int L, int P, int p) {
+  const int g = L - fft_freq(L, P, p);
+  if (g >= L / 2) return -1;
+  const int NS = fft_nstages(L, P);
+  int q = 0, mult = 1;
+  for (int t = 0; t < NS; ++t) {
+    const int r = fft_radix(L, P, t);
+    q += ((g / mult) % r) * fft_stride(L, P, t);
+    mult *= r;
+  }
+  const int R = fft_radix(L, P, NS - 1);
+  return (q / R) * (R / 2) + q % R;
+}
+
 // x[q] *= w^q for q = 1..R-1, with w^q built from the one loaded root w by
 // squarings and products (at most five roundings deep for R = 16) instead of
 // R-1 table loads: fewer live registers and one memory latency per butterfly.

@@ -78,6 +78,15 @@ static double run_case(unsigned seed) {
     }
   for (int c = 0; c < L / 2; ++c)
     if (L >= 2 && sseen[c] != 1) { printf("slots not a bijection L=%d\n", L); return 1e9; }
+  // mirrored slots of the upper half against a search over all slots
+  for (int p = 0; p < L; ++p) {
+    const int f = fft_freq(L, P, p);
+    if (f < L / 2) continue;
+    int want = -1;
+    for (int c = 0; c < L / 2; ++c)
+      if (L - f != L / 2 && fft_freq(L, P, fft_slot_pos(L, P, c)) == L - f) want = c;
+    if (fft_mirror_slot(L, P, p) != want) { printf("mirror slot wrong L=%d p=%d\n", L, p); return 1e9; }
+  }
   // inverse sweep
   for (int t = F::NS - 1; t >= 0; --t) { (void)t; }
   static_for<F::NS>([&](auto tt) {

@@ -87,7 +87,7 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
                            size_t bstride, hipStream_t s);
 // Pass C: inverse row transforms of P1, P2 and the mask combine -> z (FP64).
 template <typename T>
-hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirror,
+hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw,
                               int n1, int n2, hipStream_t s);
 
@@ -95,7 +95,7 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
 // t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL).
 template <typename T>
-hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2, const int* mirror,
+hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, hipStream_t s);

@@ -7,10 +7,10 @@ template hipError_t launch_pc_rows_fwd<float>(int, const double*, const double*,
 template hipError_t launch_pc_cols<float>(int, const float*, float*, float*, const float*, const float*,
                                         const void*, int, int, double, double, double, double,
                                         hipStream_t);
-template hipError_t launch_pc_rows_inv<float>(int, const float*, const float*, const int*,
+template hipError_t launch_pc_rows_inv<float>(int, const float*, const float*,
                                             const uint8_t*, double*, const void*, int, int,
                                             hipStream_t);
-template hipError_t launch_pc_rows_inv_mv<float>(int, const float*, const float*, const int*,
+template hipError_t launch_pc_rows_inv_mv<float>(int, const float*, const float*,
                                              const uint8_t*, double*, double*, const void*,
                                              const void*, const double*, double, double,
                                              const double*, double, int, int, hipStream_t);

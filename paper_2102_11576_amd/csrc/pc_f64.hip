@@ -7,10 +7,10 @@ template hipError_t launch_pc_rows_fwd<double>(int, const double*, const double*
 template hipError_t launch_pc_cols<double>(int, const double*, double*, double*, const double*, const double*,
                                         const void*, int, int, double, double, double, double,
                                         hipStream_t);
-template hipError_t launch_pc_rows_inv<double>(int, const double*, const double*, const int*,
+template hipError_t launch_pc_rows_inv<double>(int, const double*, const double*,
                                             const uint8_t*, double*, const void*, int, int,
                                             hipStream_t);
-template hipError_t launch_pc_rows_inv_mv<double>(int, const double*, const double*, const int*,
+template hipError_t launch_pc_rows_inv_mv<double>(int, const double*, const double*,
                                              const uint8_t*, double*, double*, const void*,
                                              const void*, const double*, double, double,
                                              const double*, double, int, int, hipStream_t);

@@ -14,7 +14,7 @@
 // the spectrum is 2 sigma_b - 2i sigma_a, both parts odd in frequency.  Pass A
 // stores only the lower half of the digit-reversed spectrum ("slots", n+1 per
 // row: frequencies 0..n, frequency 0 being identically zero); pass B works on
-// slot columns; pass C rebuilds the upper half by odd symmetry (table `mirror`)
+// slot columns; pass C rebuilds the upper half by odd symmetry (fft_mirror_slot)
 // and runs the inverse sweep, which yields the DST directly in natural order.
 // T = double or float sets the arithmetic of all three passes (the input and
 // output vectors are always FP64).
@@ -269,11 +269,10 @@ __device__ __forceinline__ void stage_slots(const T* p1, const T* p2, bool vr, i
 }
 
 // The inverse sweep's input from the staged slots: P2/2 - i P1/2 on the lower
-// half of the spectrum, the odd mirror (table `mirror`) on the upper half; a
-// barrier follows, since the sweep reuses the region.
+// half of the spectrum, the odd mirror (slot computed by fft_mirror_slot) on
+// the upper half; a barrier follows, since the sweep reuses the region.
 template <typename T, class F>
-__device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, const int* __restrict__ mirror,
-                                                     int tau, int ld, T* my) {
+__device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, int tau, int ld, T* my) {
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     constexpr int R = F::radix(F::NS - 1);
@@ -282,7 +281,7 @@ __device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, const int* __r
       reg[e].re = (T)0.5 * my[ld + slot];
       reg[e].im = (T)-0.5 * my[slot];
     } else {
-      const int ms = mirror[F::pos(F::NS - 1, tau, e)];
+      const int ms = fft_mirror_slot(1 << F::LOGL, F::PP, F::pos(F::NS - 1, tau, e));
       reg[e].re = ms >= 0 ? (T)-0.5 * my[ld + ms] : (T)0;
       reg[e].im = ms >= 0 ? (T)0.5 * my[ms] : (T)0;
     }
@@ -296,7 +295,7 @@ __device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, const int* __r
 // --------------------------------------------------------------------------
 template <typename T, int L>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
-    const T* __restrict__ P1, const T* __restrict__ P2, const int* __restrict__ mirror,
+    const T* __restrict__ P1, const T* __restrict__ P2,
     const uint8_t* __restrict__ mask, double* __restrict__ z, const cpx<T>* __restrict__ tw,
     int n1, int n2) {
   using C = PcCfg<L>;
@@ -312,7 +311,7 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
   T* my = lds + b * lds_len(L);
   stage_slots<T, F>(p1, p2, vr, ld, tau, my);
   cpx<T> reg[F::PP];
-  load_staged_spectrum<T, F>(reg, mirror, tau, ld, my);
+  load_staged_spectrum<T, F>(reg, tau, ld, my);
   fft_inverse<T, F>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -338,7 +337,7 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
 template <typename T, int L>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4)))
 void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
-                      const int* __restrict__ mirror, const uint8_t* __restrict__ mask,
+                      const uint8_t* __restrict__ mask,
                       double* __restrict__ z, double* __restrict__ t,
                       const cpx<T>* __restrict__ twT, const cpx<double>* __restrict__ tw64,
                       const double* __restrict__ sym, double coef, double dpen,
@@ -358,12 +357,11 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     // opaque copies: no per-point address is hoisted out of the loop
     const T* P1h = P1;
     const T* P2h = P2;
-    const int* mih = mirror;
     const cpx<T>* twh = twT;
     double* zh = z;
     const uint8_t* mh = mask;
     int th = tau;
-    asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(mih), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
+    asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
     const int r = ra + h;
     const bool vr = r < n2;
     const T* p1 = P1h + (size_t)r * ld;
@@ -372,7 +370,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     __syncthreads();  // the previous row's sweep may still read the region
     stage_slots<T, F>(p1, p2, vr, ld, th, myT);
     cpx<T> reg[F::PP];
-    load_staged_spectrum<T, F>(reg, mih, th, ld, myT);
+    load_staged_spectrum<T, F>(reg, th, ld, myT);
     fft_inverse<T, F>(reg, th, twh, myT);
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
@@ -446,18 +444,18 @@ static hipError_t pc_cols_impl(const T* Q, T* P1, T* P2, const T* lamx, const T*
 }
 
 template <typename T, int L>
-static hipError_t pc_rows_inv_impl(const T* P1, const T* P2, const int* mirror,
+static hipError_t pc_rows_inv_impl(const T* P1, const T* P2,
                                    const uint8_t* mask, double* z, const void* tw, int n1, int n2,
                                    hipStream_t s) {
   using C = PcCfg<L>;
   const int blocks = (n2 + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2, mirror,
+  hipLaunchKernelGGL((k_pc_rows_inv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
                      mask, z, (const cpx<T>*)tw, n1, n2);
   return hipGetLastError();
 }
 
 template <typename T, int L>
-static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2, const int* mirror,
+static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
                                       const uint8_t* mask, double* z, double* t, const void* twT,
                                       const void* tw64, const double* sym, double coef,
                                       double dpen, const double* sub, double theta, int n1,
@@ -465,7 +463,7 @@ static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2, const int* mirro
   using C = PcCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2, mirror,
+  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
                      mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
                      sub, theta, n1, n2);
   return hipGetLastError();
@@ -532,13 +530,13 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 }
 
 template <typename T>
-hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirror,
+hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw, int n1, int n2,
                               hipStream_t s) {
   switch (Lx) {
 #define X(LL) \
   case LL:    \
-    return pc_rows_inv_impl<T, LL>(P1, P2, mirror, mask, z, tw, n1, n2, s);
+    return pc_rows_inv_impl<T, LL>(P1, P2, mask, z, tw, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -547,14 +545,14 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2, const int* mirro
 }
 
 template <typename T>
-hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2, const int* mirror,
+hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, hipStream_t s) {
   switch (L) {
 #define X(LL) \
   case LL:    \
-    return pc_rows_inv_mv_impl<T, LL>(P1, P2, mirror, mask, z, t, twT, tw64, sym, coef, dpen, sub, \
+    return pc_rows_inv_mv_impl<T, LL>(P1, P2, mask, z, t, twT, tw64, sym, coef, dpen, sub, \
                                       theta, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X

@@ -108,7 +108,6 @@ struct Plan {
   double* lamy64 = nullptr;
   float* lamx32 = nullptr;
   float* lamy32 = nullptr;
-  int* mirror = nullptr;
   // chirp-form preconditioner (n + 1 not a power of two)
   double* lamx_n = nullptr;  // tau eigenvalues, natural order, unit k
   double* lamy_n = nullptr;
@@ -498,13 +497,13 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
   if (!w || P->Ldx != P->Lcx) {  // unfused (n1 = 1: convolution and sine lengths differ)
     {
       ProfScope ps(P, s, kCatPcRowsInv, 2.0 * ts * S + 9.0 * N);
-      CK(launch_pc_rows_inv<T>(P->Ldx, Q, R, P->mirror, P->mask, z, tw[P->Ldx], n1, rows, s));
+      CK(launch_pc_rows_inv<T>(P->Ldx, Q, R, P->mask, z, tw[P->Ldx], n1, rows, s));
     }
     return w ? matvec_impl(P, z, w, s, sub, theta) : RSFDE_OK;
   }
   {
     ProfScope ps(P, s, kCatPcInvMv, 2.0 * ts * S + 17.0 * N + (sub ? 8.0 * N : 0.0));
-    CK(launch_pc_rows_inv_mv<T>(P->Ldx, Q, R, P->mirror, P->mask, z, P->t, tw[P->Ldx],
+    CK(launch_pc_rows_inv_mv<T>(P->Ldx, Q, R, P->mask, z, P->t, tw[P->Ldx],
                                 P->tw64[P->Ldx], P->symx, -P->kx, P->dpen, sub, theta, n1, rows,
                                 s));
   }
@@ -547,7 +546,7 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 16.0 * S + 9.0 * N);
-      CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw64[P->Ldx],
+      CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mask, z, P->tw64[P->Ldx],
                                     P->n1, P->n2, s));
     }
     return RSFDE_OK;
@@ -565,7 +564,7 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 8.0 * S + 9.0 * N);
-      CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->tw32[P->Ldx],
+      CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mask, z, P->tw32[P->Ldx],
                                    P->n1, P->n2, s));
     }
     return RSFDE_OK;
@@ -610,7 +609,7 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 16.0 * S + 17.0 * N + extra);
-      CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->t,
+      CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mask, z, P->t,
                                        P->tw64[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
                                        sub, theta, P->n1, P->n2, s));
     }
@@ -627,7 +626,7 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 8.0 * S + 17.0 * N + extra);
-      CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mirror, P->mask, z, P->t,
+      CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mask, z, P->t,
                                       P->tw32[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
                                       sub, theta, P->n1, P->n2, s));
     }
@@ -1225,27 +1224,16 @@ int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) 
   return RSFDE_OK;
 }
 
-// Pass A/C tables of the power-of-two sine transform along x: eigenvalues in
-// slot order (0 at frequency 0) and the slot that mirrors each upper-half
-// register position (-1 where the spectrum is zero).
-void slot_tables(const std::vector<double>& lx, int Lx, std::vector<double>& lam,
-                 std::vector<int>& mirror) {
+// Pass A/B table of the power-of-two sine transform along x: eigenvalues in
+// slot order (0 at frequency 0).
+std::vector<double> slot_eigs(const std::vector<double>& lx, int Lx) {
   const int n1 = (int)lx.size(), Px = fft_pts(Lx);
-  lam.assign(n1 + 1, 0.0);
-  mirror.assign(Lx, -1);
-  std::vector<int> slot_of_f(Lx / 2, -1);
+  std::vector<double> lam(n1 + 1, 0.0);
   for (int c = 0; c < n1 + 1; ++c) {
     const int f = fft_freq(Lx, Px, fft_slot_pos(Lx, Px, c));
     lam[c] = (f >= 1 && f <= n1) ? lx[f - 1] : 0.0;
-    slot_of_f[f] = c;
   }
-  for (int p = 0; p < Lx; ++p) {
-    const int f = fft_freq(Lx, Px, p);
-    if (f >= Lx / 2) {
-      const int g = Lx - f;
-      mirror[p] = (g == Lx / 2) ? -1 : slot_of_f[g];
-    }
-  }
+  return lam;
 }
 
 // Column-pass eigenvalues in register-position order of the length-L FFT
@@ -1363,14 +1351,11 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
 
   // Preconditioner tables (Section 4.1), in the layouts of the three passes.
   if (P->Ldx && P->Ldy) {
-    std::vector<double> lamx;
-    std::vector<int> mirror;
-    slot_tables(tau_eigs(tx), P->Ldx, lamx, mirror);
+    const std::vector<double> lamx = slot_eigs(tau_eigs(tx), P->Ldx);
     const std::vector<double> lamy = pos_eigs(tau_eigs(ty), P->Ldy);
     std::vector<float> lamx_f(lamx.begin(), lamx.end()), lamy_f(lamy.begin(), lamy.end());
     if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
-        upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess ||
-        upload(P, &P->mirror, mirror, s) != hipSuccess)
+        upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess)
       return fail(RSFDE_ENOMEM);
   }
   if (P->Lgx) {  // chirp-form tables
@@ -1504,9 +1489,7 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
     if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
   // Section 4.1's eigenvalues: x in slot order folded with y into one value per
   // column of the [n3][(n1+1) n2] view (k included), z in position order (unit kz).
-  std::vector<double> lamx;
-  std::vector<int> mirror;
-  slot_tables(tau_eigs(t[0]), P->Ldx, lamx, mirror);
+  const std::vector<double> lamx = slot_eigs(tau_eigs(t[0]), P->Ldx);
   const std::vector<double> ly = tau_eigs(t[1]);
   std::vector<double> lamc((size_t)(n[0] + 1) * n[1]);
   for (int j = 0; j < n[1]; ++j)
@@ -1514,8 +1497,7 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
   const std::vector<double> lamz = pos_eigs(tau_eigs(t[2]), P->Ldz);
   const std::vector<float> lamc_f(lamc.begin(), lamc.end()), lamz_f(lamz.begin(), lamz.end());
   if (upload(P, &P->lamc64, lamc, s) != hipSuccess || upload(P, &P->lamc32, lamc_f, s) != hipSuccess ||
-      upload(P, &P->lamz64, lamz, s) != hipSuccess || upload(P, &P->lamz32, lamz_f, s) != hipSuccess ||
-      upload(P, &P->mirror, mirror, s) != hipSuccess)
+      upload(P, &P->lamz64, lamz, s) != hipSuccess || upload(P, &P->lamz32, lamz_f, s) != hipSuccess)
     return fail(RSFDE_ENOMEM);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(RSFDE_EHIP);
   *out = h;
