@@ -38,6 +38,7 @@ struct KrylovState {
   double g[kMaxRestart + 1];
   double vscale[kMaxRestart + 1];             // V_i is stored unnormalised: v_i = vscale[i] * V_i
   double h2[kMaxRestart + 1];                 // second Gram-Schmidt pass (reorthogonalisation)
+  int32_t gram_done;                          // blocks of a Gram finish done (0 between launches)
 };
 constexpr int kLdH = kMaxRestart + 1;
 
@@ -163,9 +164,11 @@ constexpr int kGramBlocks = 1024;
 constexpr int kGramMaxTiles = 5;  // up to 80 Gram rows
 // After G is written and fenced, the finishing kernel stores seq to *seq_flag
 // (pinned host memory), so that the host can wait for G by polling that word.
+// done_count: a device word that is 0 between launches (the finishing
+// kernel's blocks count themselves on it and the last one resets it).
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, int32_t* seq_flag, int32_t seq,
-                        hipStream_t st);
+                        int32_t* done_count, hipStream_t st);
 // V_{m1..m1+s-1} <- (V_{m1..} - V_{0..nq-1} C) R^{-1}; coef = C [nq][s] then R^{-1} [s][s]
 // (nq*s + s*s doubles).  Up to kCoefArgMax coefficients travel as kernel
 // arguments (coef is then a host pointer); more are read from coef_dev, which

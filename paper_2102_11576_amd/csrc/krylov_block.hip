@@ -102,14 +102,16 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 }
 
 // G[r * 16 + c] = sum of the partials (fixed order), written where the host
-// reads it (pinned, device-visible memory).
-// Then every writer fences at system scope, and thread 0 publishes seq.
+// reads it (pinned, device-visible memory); one wavefront per entry, spread
+// over a grid.  Every block fences its entries at system scope and counts
+// itself on *done; the last block resets the count and publishes seq.
 __global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* __restrict__ gpart,
                                                                  int nr, int s, int nb,
                                                                  double* G, int32_t* seq_flag,
-                                                                 int32_t seq) {
+                                                                 int32_t seq, int32_t* done) {
   const int lane = threadIdx.x & 63;
-  for (int p = threadIdx.x >> 6; p < nr * s; p += kFinishThreads / 64) {
+  constexpr int kWaves = kFinishThreads / 64;
+  for (int p = blockIdx.x * kWaves + (threadIdx.x >> 6); p < nr * s; p += gridDim.x * kWaves) {
     const int r = p / s, c = p % s;
     const double* src = gpart + (size_t)(r * 16 + c) * kGramBlocks;
     double x = 0.0;
@@ -120,8 +122,12 @@ __global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* _
   __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence_system();
-    *reinterpret_cast<volatile int32_t*>(seq_flag) = seq;
+    const int prior = atomicAdd(done, 1);
+    if (prior == (int)gridDim.x - 1) {  // every block's entries are written and fenced
+      atomicExch(done, 0);
+      __threadfence_system();
+      *reinterpret_cast<volatile int32_t*>(seq_flag) = seq;
+    }
   }
 }
 
@@ -201,7 +207,7 @@ __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, si
 
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, int32_t* seq_flag, int32_t seq,
-                        hipStream_t st) {
+                        int32_t* done_count, hipStream_t st) {
   if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
   int nb = (int)((N / 32 + 4 * 4 - 1) / (4 * 4));  // >= 4 chunks per wave
   if (nb < 1) nb = 1;
@@ -215,8 +221,9 @@ hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_
     case 5: hipLaunchKernelGGL(k_bgram<5>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_bgram_finish, dim3(1), dim3(kFinishThreads), 0, st, gpart, nr, s, nb,
-                     G_host_dev, seq_flag, seq);
+  const int fb = (nr * s + kFinishThreads / 64 - 1) / (kFinishThreads / 64);
+  hipLaunchKernelGGL(k_bgram_finish, dim3(fb), dim3(kFinishThreads), 0, st, gpart, nr, s, nb,
+                     G_host_dev, seq_flag, seq, done_count);
   return hipGetLastError();
 }
 

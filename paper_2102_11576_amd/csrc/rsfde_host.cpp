@@ -905,7 +905,7 @@ int gram_block(Plan* P, int nr, int nq, int ss, hipStream_t s) {
   {
     ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)P->N);
     CK(launch_bgram(P->V, P->ldv, nr, nq, ss, P->N, P->gpart, P->gram_d, &P->hs_dev->gram_seq,
-                    seq, s));
+                    seq, &P->ks->gram_done, s));
   }
   for (unsigned it = 1;; ++it) {
     if (vread(&P->hs->gram_seq) == seq) return RSFDE_OK;
