@@ -187,5 +187,8 @@ hipError_t launch_dot_accum(const double* a, const double* b, size_t N, RedWork 
                             int counter_slot, double* acc, hipStream_t s);
 
 int red_blocks(size_t N);
+// Grid of a streaming kernel without a cross-block reduction (grid-stride
+// loops over double2 pairs): up to 4096 blocks, for memory-level parallelism.
+int stream_blocks(size_t N);
 
 }  // namespace rsfde

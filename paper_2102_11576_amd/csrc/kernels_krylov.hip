@@ -12,6 +12,13 @@
 
 namespace rsfde {
 
+int stream_blocks(size_t N) {
+  size_t b = (N / 2 + (size_t)kRedThreads - 1) / (size_t)kRedThreads;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
 int red_blocks(size_t N) {
   size_t b = (N + (size_t)kRedThreads * 16 - 1) / ((size_t)kRedThreads * 16);
   if (b < 1) b = 1;

@@ -229,7 +229,7 @@ hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_
 
 hipError_t launch_bupd(double* V, size_t ld, int nq, int m1, int s, size_t N, const double* coef,
                        const double* coef_dev, hipStream_t st) {
-  const dim3 g(red_blocks(N)), b(kRedThreads);
+  const dim3 g(stream_blocks(N)), b(kRedThreads);
   const size_t nc = (size_t)nq * s + (size_t)s * s;
   const bool by_args = nc <= (size_t)kCoefArgMax;
   CoefArgs a;

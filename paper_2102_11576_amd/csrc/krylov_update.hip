@@ -80,7 +80,7 @@ hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t 
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
     kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, false, none,
-                   dim3(red_blocks(N)), s);
+                   dim3(stream_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -96,7 +96,7 @@ hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, si
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
     kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, nullptr, v0, jc, false, true, cg,
-                   dim3(red_blocks(N)), s);
+                   dim3(stream_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
