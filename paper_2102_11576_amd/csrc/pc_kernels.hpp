@@ -352,6 +352,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
   const bool va = ra < n2, vb = rb < n2;
   const int ld = n1 + 1;
   double* my = lds + b * lds_len(L);
+  double zb[F::PP];  // row b's z at this thread's positions, kept for the convolution
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     // opaque copies: no per-point address is hoisted out of the loop
@@ -375,21 +376,25 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
       const int p = F::pos(0, th, e);
+      double zv = 0.0;
       if (vr && p >= 1 && p <= n1) {
         const size_t i = (size_t)r * n1 + (p - 1);
-        zh[i] = mh[i] ? (double)reg[e].re : (double)reg[e].im;
+        zv = mh[i] ? (double)reg[e].re : (double)reg[e].im;
+        zh[i] = zv;
       }
+      if (h == 1) zb[e] = zv;
     });
   }
-  __threadfence_block();
-  __syncthreads();
+  // Convolution input z_a + i z_b at the sweep's own positions: row b from
+  // registers, row a read back where this same thread stored it (no other
+  // thread's write is involved, so no barrier is needed).
   cpx<double> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
     const bool in = p >= 1 && p <= n1;
     reg[e].re = (va && in) ? z[(size_t)ra * n1 + (p - 1)] : 0.0;
-    reg[e].im = (vb && in) ? z[(size_t)rb * n1 + (p - 1)] : 0.0;
+    reg[e].im = zb[e];
   });
   fft_forward<double, F>(reg, tau, tw64, my);
   static_for<F::PP>([&](auto ee) {
