@@ -1,5 +1,5 @@
-"""GPU parity at the full benchmark sizes (2047^2 and 4095^2), in the launch
-configuration bench.py times.
+"""GPU parity at the full configuration sizes (1023^2, 2047^2 and 4095^2), in
+the launch configuration bench.py times.
 
 * matvec: whole output against the oracle's FFT-Toeplitz form (2047^2) and
   sampled entries summed directly from the Toeplitz rows (4095^2);
@@ -98,3 +98,24 @@ def test_full_4095_matvec_samples_precond_and_step():
     b = O.rhs(p, w.u0, w.f_kind)
     r = b - O.matvec_fast(p, u)
     assert np.linalg.norm(r) <= (w.tol + 1e-12) * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("sstep", [0, 10])
+def test_full_1023_matvec_precond_and_step(sstep):
+    """The 1023^2 ellipse configuration (alpha = 1.2/1.8, ky = 0.5, GMRES(30) to
+    1e-8): whole matvec and FP64 preconditioner against the oracle's FFT forms,
+    and one step's true residual, in both GMRES forms."""
+    w = make_config("c2")
+    p = O.problem_from_workload(w)
+    Z = np.random.default_rng(5).standard_normal((w.n2, w.n1))
+    with RsfdePlan.from_workload(w) as pl:
+        out = pl.matvec(_t(Z)).cpu().numpy().reshape(w.n2, w.n1)
+        assert np.abs(out - O.matvec_fast(p, Z)).max() <= 1e-13 * _norm_M_inf(p) * np.abs(Z).max()
+        zp = pl.precond(_t(Z)).cpu().numpy().reshape(w.n2, w.n1)
+        assert np.linalg.norm(zp - O.precond_apply_fft(p, Z)) <= 1e-13 * np.linalg.norm(Z)
+        u1, st = pl.step(_t(w.u0), None, w.f_kind, make_opts(w.restart, 100000, w.tol, sstep=sstep))
+        u = u1.cpu().numpy().reshape(w.n2, w.n1)
+    b = O.rhs(p, w.u0, w.f_kind)
+    r = b - O.matvec_fast(p, u)
+    assert np.linalg.norm(r) <= (w.tol + 1e-12) * np.linalg.norm(b)
+    assert st.iters > 0
