@@ -100,7 +100,10 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-three-d", action="store_true")
-    ap.add_argument("--mode", choices=["march", "kernels", "ablations", "three_d"], default="march",
+    ap.add_argument("--ex1-sizes", default="128,256,512,1024,2048,4096",
+                    help="grid sizes of --mode example1")
+    ap.add_argument("--mode", choices=["march", "kernels", "ablations", "three_d", "example1"],
+                    default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-ensemble", action="store_true")
@@ -356,6 +359,61 @@ def three_d_rate(log, sstep=10, steps=4, profile=True, one_vector=True, fp32=Tru
     return res
 
 
+def example1_large(args):
+    """The paper's Example 1 (Section 5: ellipse a = 2, b = 1 in (0,4) x (0,2),
+    alpha = (1.4, 1.7), kx = ky = 1, eta = 1e-5, T = 1 with m = n1 steps,
+    manufactured source, paper mode: left preconditioning, GMRES(20), tol 1e-8)
+    on the GPU from the table sizes up to n1 = 4096 (n1 + 1 is not a power of
+    two, so the chirp-form sine transforms run).  Per size: mean iterations per
+    step, the error against the exact solution inside the domain (max norm,
+    relative) and its ratio to the previous size (first order: about 2), time
+    and unknown*timesteps/s.  One JSON line."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from workloads.configs import example1_workload
+    sizes = [int(v) for v in args.ex1_sizes.split(",")]
+    dev = torch.device("cuda:0")
+    rows, prev = [], None
+    for n in sizes:
+        w = example1_workload(n, 1.0)
+        dt = w.T / w.m
+        opts = make_opts(w.restart, 10000, w.tol, "fp64", side="left")
+        with RsfdePlan.from_workload(w, device=dev) as pl:
+            u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+            src = torch.as_tensor(w.extra["src"], device=dev).reshape(-1).contiguous()
+            pl.march(u0, 2, w.f_kind, opts, src=src, src_scale=lambda k: math.exp(-(k - 1) * dt))
+            torch.cuda.synchronize()
+            # the march of solver.RsfdePlan.march, stepped here to report progress
+            bufs = [u0.clone(), pl.empty(), pl.empty()]
+            cur, prv, iters = 0, None, []
+            t0 = time.perf_counter()
+            for k in range(1, w.m + 1):
+                nxt = [i for i in range(3) if i != cur and i != prv][0]
+                _, st = pl.step(bufs[cur], None if prv is None else bufs[prv], w.f_kind, opts,
+                                bufs[nxt], src=src, src_scale=math.exp(-(k - 1) * dt))
+                iters.append(st.iters)
+                prv, cur = cur, nxt
+                if k % 512 == 0 and k < w.m:
+                    log(f"example 1, n1 = {n}: step {k} of {w.m}")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            u = bufs[cur].cpu().numpy().reshape(n, n)
+        ue = math.exp(-w.T) * w.extra["exact0"]
+        inside = w.mask.astype(bool)
+        err = float(np.abs(ue - u)[inside].max() / np.abs(ue)[inside].max())
+        row = {"n1": n, "steps": w.m, "iter_mean": float(np.mean(iters)), "rel_err_max": err,
+               "err_ratio_to_previous": (prev / err) if prev else None, "seconds": el,
+               "unknown_timesteps_per_s": n * n * w.m / el}
+        prev = err
+        rows.append(row)
+        log(f"example 1, n1 = {n}: {w.m} steps in {el:.1f} s, Iter {row['iter_mean']:.2f}, "
+            f"error {err:.3e}" + (f" (ratio {row['err_ratio_to_previous']:.2f})" if row['err_ratio_to_previous'] else ""))
+    print(json.dumps({"example1": rows, "note": "paper mode (left preconditioning, GMRES(20), "
+                      "tol 1e-8 on the preconditioned residual), kx = ky = 1, T = 1, m = n1"}))
+
+
 def traffic_for(kernel, bytes_per_launch):
     """Measured HBM bytes per launch of `kernel` from the committed counter
     summary, if it was taken on the current kernel sources (else None)."""
@@ -419,6 +477,9 @@ def main():
         return
     if args.mode == "ablations":
         ablations(args)
+        return
+    if args.mode == "example1":
+        example1_large(args)
         return
     if args.mode == "three_d":  # the 3-D leg alone (for kernel traces)
         print(json.dumps({"three_d": three_d_rate(log, args.sstep, args.steps or 4,
