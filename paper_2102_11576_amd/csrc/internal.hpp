@@ -66,16 +66,21 @@ hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           size_t bstride = 0);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
+// tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q and the
+// interleaved P1/P2 pairs (array P1, P2 unused) are strip-tiled ([2 rows][4
+// slots] tiles, strip after strip; Q holds 4 ceil((n1+1)/4) ceil(n2/2) T
+// values, P1 twice as many).
 // Pass A: Q[r][slot] = raw x-sine sums of (sig * v) rows.
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q,
-                              const void* tw, int n1, int n2, hipStream_t s);
+                              const void* tw, int n1, int n2, bool tiled, hipStream_t s);
 // Pass B: column sine transforms of Q, the two eigenvalue scalings, two inverse
 // column transforms -> P1, P2 (slot layout in x, natural rows in y).
 template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2,
-                          double kx, double ky, double dpen, double Kfac, hipStream_t s);
+                          double kx, double ky, double dpen, double Kfac, bool tiled,
+                          hipStream_t s);
 // Raw sine transform (DST-I without normalisation) along the columns of
 // `batch` slices of [rows][ld] values (slice b at offset b * bstride):
 //   outA[k-1][ca] = sum_{p=1..rows} inA[p-1][ca] sin(pi k p / (rows + 1)), k = 1..rows,
@@ -90,7 +95,7 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw,
-                              int n1, int n2, hipStream_t s);
+                              int n1, int n2, bool tiled, hipStream_t s);
 
 // Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
@@ -99,7 +104,8 @@ template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
-                                 const double* sub, double theta, int n1, int n2, hipStream_t s);
+                                 const double* sub, double theta, int n1, int n2, bool tiled,
+                                 hipStream_t s);
 
 // Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
 // power of two): T internals, tables chn (n entries) and khat (L entries, in

@@ -18,10 +18,35 @@
 // and runs the inverse sweep, which yields the DST directly in natural order.
 // T = double or float sets the arithmetic of all three passes (the input and
 // output vectors are always FP64).
+//
+// Layout of the intermediates.  Natural (TL = false): Q, P1, P2 are
+// [rows][n+1] arrays.  Strip-tiled (TL = true, the two-dimensional plans):
+// tiles of [2 rows][4 slots], the tiles of one 4-slot strip stored row pair
+// after row pair and the strips one after another, with P1 and P2
+// interleaved (P1 at 2i, P2 at 2i + 1 of one array).  Pass B then reads and
+// writes whole strips contiguously, where the natural layout gives it 32-byte
+// pieces of rows 8 (n+1) bytes apart; the row passes move 64-byte pieces (a
+// row pair's 4 slots of Q, one row's P1/P2 pairs for 4 slots).
 #pragma once
 #include "fft_common.hpp"
 
 namespace rsfde {
+
+// Element of (row r, slot c) in the strip-tiled layout; hp = row pairs per
+// strip (ceil(rows / 2)).
+__device__ __forceinline__ size_t tile_index(int r, int c, int hp) {
+  return ((size_t)(c >> 2) * hp + (r >> 1)) * 8 + (r & 1) * 4 + (c & 3);
+}
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
 
 template <int L>
 struct PcCfg {
@@ -41,7 +66,7 @@ struct PcColCfg {
 // --------------------------------------------------------------------------
 // Pass A: row pairs (ra, rb) -> Q rows (n1+1 slots each).
 // --------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
     const double* __restrict__ v, const double* __restrict__ sig, T* __restrict__ Q,
     const cpx<T>* __restrict__ tw, int n1, int n2) {
@@ -101,18 +126,34 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
     }
   });
   __syncthreads();
-  static_for<F::PP / 2>([&](auto kk) {
-    constexpr int k = decltype(kk)::value;
-    const int j = tau + k * F::TPF;  // < L/2 = ld
-    if (va) Q[(size_t)ra * ld + j] = my[j];
-    if (vb) Q[(size_t)rb * ld + j] = my[ld + j];
-  });
+  if constexpr (TL) {
+    // Element j of this row pair's tiles: strip j / 8, row w / 4, slot 4 (j / 8) + w % 4
+    // (w = j % 8); a missing row b (odd n2) is stored as the zeros staged for it.
+    constexpr int NT = (8 * ((L / 2 + 3) / 4) + F::TPF - 1) / F::TPF;
+    const int hp = (n2 + 1) >> 1;
+    if (va) {
+      T* qp = Q + (size_t)pair * 8;
+      static_for<NT>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const int j = tau + k * F::TPF;
+        const int g = j >> 3, w = j & 7, c = 4 * g + (w & 3);
+        if (c < ld) qp[(size_t)g * hp * 8 + w] = my[(w >> 2) * ld + c];
+      });
+    }
+  } else {
+    static_for<F::PP / 2>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int j = tau + k * F::TPF;  // < L/2 = ld
+      if (va) Q[(size_t)ra * ld + j] = my[j];
+      if (vb) Q[(size_t)rb * ld + j] = my[ld + j];
+    });
+  }
 }
 
 // --------------------------------------------------------------------------
 // Pass B: slot-column pairs (ca, cb) of Q -> P1, P2 columns.
 // --------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     const T* __restrict__ Q, T* __restrict__ P1, T* __restrict__ P2,
     const T* __restrict__ lamx_slot, const T* __restrict__ lamy_pos,
@@ -125,8 +166,9 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
   const int cp = strip * C::BC + b;
   const int ca = 2 * cp, cb = 2 * cp + 1;
-  const int ld = n1 + 1;
+  const int ld = n1 + 1, hp = (n2 + 1) >> 1;
   const bool valid = cb < ld;  // n1 + 1 is even: both or neither
+  using V2 = typename Vec2<T>::type;
   cpx<T> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -140,8 +182,15 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
       sgn = (T)-1;
     }
     const bool ok = valid && row >= 0;
-    reg[e].re = ok ? sgn * Q[(size_t)row * ld + ca] : (T)0;
-    reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
+    if constexpr (TL) {
+      // ca is even: (ca, cb) are adjacent elements of one tile row
+      const V2 q = ok ? *(const V2*)(Q + tile_index(row, ca, hp)) : V2{(T)0, (T)0};
+      reg[e].re = sgn * q.x;
+      reg[e].im = sgn * q.y;
+    } else {
+      reg[e].re = ok ? sgn * Q[(size_t)row * ld + ca] : (T)0;
+      reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
+    }
   });
   T* my = lds + b;  // regions interleaved (stride BC)
   // (no register materialisation between the sweeps here: it measured slower)
@@ -167,9 +216,13 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
     if (valid && p >= 1 && p <= n2) {
-      const size_t i = (size_t)(p - 1) * ld + ca;
-      P1[i] = reg[e].re;
-      P2[i] = reg[e].im;
+      if constexpr (TL) {
+        *(V2*)(P1 + 2 * tile_index(p - 1, ca, hp)) = V2{reg[e].re, reg[e].im};
+      } else {
+        const size_t i = (size_t)(p - 1) * ld + ca;
+        P1[i] = reg[e].re;
+        P2[i] = reg[e].im;
+      }
     }
   });
   // Hide the table pointer from the optimiser so that the second sweep reloads
@@ -191,9 +244,13 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
     if (valid && p >= 1 && p <= n2) {
-      const size_t i = (size_t)(p - 1) * ld + cb;
-      P1[i] = reg[e].re;
-      P2[i] = reg[e].im;
+      if constexpr (TL) {
+        *(V2*)(P1 + 2 * tile_index(p - 1, cb, hp)) = V2{reg[e].re, reg[e].im};
+      } else {
+        const size_t i = (size_t)(p - 1) * ld + cb;
+        P1[i] = reg[e].re;
+        P2[i] = reg[e].im;
+      }
     }
   });
 }
@@ -268,6 +325,22 @@ __device__ __forceinline__ void stage_slots(const T* p1, const T* p2, bool vr, i
   __syncthreads();
 }
 
+// The same from the strip-tiled layout (P1/P2 pairs of row r at
+// 2 tile_index(r, j, hp)): one 2-vector load per slot.
+template <typename T, class F>
+__device__ __forceinline__ void stage_slots_tiled(const T* pp, int r, bool vr, int ld, int hp,
+                                                  int tau, T* my) {
+  using V2 = typename Vec2<T>::type;
+  static_for<F::PP / 2>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const int j = tau + k * F::TPF;  // < L/2 = ld
+    const V2 q = vr ? *(const V2*)(pp + 2 * tile_index(r, j, hp)) : V2{(T)0, (T)0};
+    my[j] = q.x;
+    my[ld + j] = q.y;
+  });
+  __syncthreads();
+}
+
 // The inverse sweep's input from the staged slots: P2/2 - i P1/2 on the lower
 // half of the spectrum, the odd mirror (slot computed by fft_mirror_slot) on
 // the upper half; a barrier follows, since the sweep reuses the region.
@@ -293,7 +366,7 @@ __device__ __forceinline__ void load_staged_spectrum(cpx<T>* reg, int tau, int l
 // Pass C: one row r per FFT; spectrum P2/2 - i P1/2 on the lower half, odd
 // mirror on the upper half; the inverse sweep gives (P1 S_x) + i (P2 S_x).
 // --------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
     const T* __restrict__ P1, const T* __restrict__ P2,
     const uint8_t* __restrict__ mask, double* __restrict__ z, const cpx<T>* __restrict__ tw,
@@ -306,10 +379,11 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
   const int r = blockIdx.x * C::BR + b;
   const bool vr = r < n2;
   const int ld = n1 + 1;
-  const T* p1 = P1 + (size_t)r * ld;
-  const T* p2 = P2 + (size_t)r * ld;
   T* my = lds + b * lds_len(L);
-  stage_slots<T, F>(p1, p2, vr, ld, tau, my);
+  if constexpr (TL)
+    stage_slots_tiled<T, F>(P1, r, vr, ld, (n2 + 1) >> 1, tau, my);
+  else
+    stage_slots<T, F>(P1 + (size_t)r * ld, P2 + (size_t)r * ld, vr, ld, tau, my);
   cpx<T> reg[F::PP];
   load_staged_spectrum<T, F>(reg, tau, ld, my);
   fft_inverse<T, F>(reg, tau, tw, my);
@@ -334,7 +408,7 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
 // z is placed at positions 1..n1 of the convolution (where pass C leaves it),
 // a circular shift that the convolution carries to its output.
 // --------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4)))
 void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
                       const uint8_t* __restrict__ mask,
@@ -365,11 +439,12 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
     const int r = ra + h;
     const bool vr = r < n2;
-    const T* p1 = P1h + (size_t)r * ld;
-    const T* p2 = P2h + (size_t)r * ld;
     T* myT = reinterpret_cast<T*>(my);
     __syncthreads();  // the previous row's sweep may still read the region
-    stage_slots<T, F>(p1, p2, vr, ld, th, myT);
+    if constexpr (TL)
+      stage_slots_tiled<T, F>(P1h, r, vr, ld, (n2 + 1) >> 1, th, myT);
+    else
+      stage_slots<T, F>(P1h + (size_t)r * ld, P2h + (size_t)r * ld, vr, ld, th, myT);
     cpx<T> reg[F::PP];
     load_staged_spectrum<T, F>(reg, th, ld, myT);
     fft_inverse<T, F>(reg, th, twh, myT);
@@ -425,41 +500,41 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
 }
 
 // ------------------------------- launchers --------------------------------
-template <typename T, int L>
+template <typename T, int L, bool TL>
 static hipError_t pc_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* tw,
                                    int n1, int n2, hipStream_t s) {
   using C = PcCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_fwd<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, v, sig, Q,
+  hipLaunchKernelGGL((k_pc_rows_fwd<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, v, sig, Q,
                      (const cpx<T>*)tw, n1, n2);
   return hipGetLastError();
 }
 
-template <typename T, int L>
+template <typename T, int L, bool TL>
 static hipError_t pc_cols_impl(const T* Q, T* P1, T* P2, const T* lamx, const T* lamy,
                                const void* tw, int n1, int n2, double kx, double ky, double dpen,
                                double Kfac, hipStream_t s) {
   using C = PcColCfg<L>;
   const int pairs = (n1 + 1) / 2;
   const int blocks = (pairs + C::BC - 1) / C::BC;
-  hipLaunchKernelGGL((k_pc_cols<T, L>), dim3(blocks), dim3(C::THR_C), 0, s, Q, P1, P2, lamx, lamy,
+  hipLaunchKernelGGL((k_pc_cols<T, L, TL>), dim3(blocks), dim3(C::THR_C), 0, s, Q, P1, P2, lamx, lamy,
                      (const cpx<T>*)tw, n1, n2, (T)kx, (T)ky, (T)dpen, (T)(0.5 * Kfac));
   return hipGetLastError();
 }
 
-template <typename T, int L>
+template <typename T, int L, bool TL>
 static hipError_t pc_rows_inv_impl(const T* P1, const T* P2,
                                    const uint8_t* mask, double* z, const void* tw, int n1, int n2,
                                    hipStream_t s) {
   using C = PcCfg<L>;
   const int blocks = (n2 + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
+  hipLaunchKernelGGL((k_pc_rows_inv<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
                      mask, z, (const cpx<T>*)tw, n1, n2);
   return hipGetLastError();
 }
 
-template <typename T, int L>
+template <typename T, int L, bool TL>
 static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
                                       const uint8_t* mask, double* z, double* t, const void* twT,
                                       const void* tw64, const double* sym, double coef,
@@ -468,7 +543,7 @@ static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
   using C = PcCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
+  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
                      mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
                      sub, theta, n1, n2);
   return hipGetLastError();
@@ -491,11 +566,12 @@ static hipError_t dst_cols_impl(const T* inA, const T* inB, T* outA, T* outB, co
 
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, const void* tw,
-                              int n1, int n2, hipStream_t s) {
+                              int n1, int n2, bool tiled, hipStream_t s) {
   switch (Lx) {
-#define X(LL) \
-  case LL:    \
-    return pc_rows_fwd_impl<T, LL>(v, sig, Q, tw, n1, n2, s);
+#define X(LL)                                                           \
+  case LL:                                                              \
+    return tiled ? pc_rows_fwd_impl<T, LL, true>(v, sig, Q, tw, n1, n2, s) \
+                 : pc_rows_fwd_impl<T, LL, false>(v, sig, Q, tw, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -506,11 +582,14 @@ hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, 
 template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2, double kx, double ky,
-                          double dpen, double Kfac, hipStream_t s) {
+                          double dpen, double Kfac, bool tiled, hipStream_t s) {
   switch (Ly) {
-#define X(LL) \
-  case LL:    \
-    return pc_cols_impl<T, LL>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, dpen, Kfac, s);
+#define X(LL)                                                                                   \
+  case LL:                                                                                      \
+    return tiled ? pc_cols_impl<T, LL, true>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, \
+                                             dpen, Kfac, s)                                     \
+                 : pc_cols_impl<T, LL, false>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx,   \
+                                              ky, dpen, Kfac, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -537,11 +616,12 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw, int n1, int n2,
-                              hipStream_t s) {
+                              bool tiled, hipStream_t s) {
   switch (Lx) {
-#define X(LL) \
-  case LL:    \
-    return pc_rows_inv_impl<T, LL>(P1, P2, mask, z, tw, n1, n2, s);
+#define X(LL)                                                                  \
+  case LL:                                                                     \
+    return tiled ? pc_rows_inv_impl<T, LL, true>(P1, P2, mask, z, tw, n1, n2, s) \
+                 : pc_rows_inv_impl<T, LL, false>(P1, P2, mask, z, tw, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -553,12 +633,15 @@ template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
-                                 const double* sub, double theta, int n1, int n2, hipStream_t s) {
+                                 const double* sub, double theta, int n1, int n2, bool tiled,
+                                 hipStream_t s) {
   switch (L) {
-#define X(LL) \
-  case LL:    \
-    return pc_rows_inv_mv_impl<T, LL>(P1, P2, mask, z, t, twT, tw64, sym, coef, dpen, sub, \
-                                      theta, n1, n2, s);
+#define X(LL)                                                                                    \
+  case LL:                                                                                       \
+    return tiled ? pc_rows_inv_mv_impl<T, LL, true>(P1, P2, mask, z, t, twT, tw64, sym, coef,    \
+                                                    dpen, sub, theta, n1, n2, s)                 \
+                 : pc_rows_inv_mv_impl<T, LL, false>(P1, P2, mask, z, t, twT, tw64, sym, coef,   \
+                                                     dpen, sub, theta, n1, n2, s);
     RSFDE_LD_CASES(X)
 #undef X
     default:

@@ -479,7 +479,7 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
   T *Q = (T*)P->Q, *R = (T*)P->R3, *P1 = (T*)P->P1, *P2 = (T*)P->P2;
   {
     ProfScope ps(P, s, kCatPcRows, 8.0 * N + ts * S);
-    CK(launch_pc_rows_fwd<T>(P->Ldx, r, sig, Q, tw[P->Ldx], n1, rows, s));
+    CK(launch_pc_rows_fwd<T>(P->Ldx, r, sig, Q, tw[P->Ldx], n1, rows, false, s));
   }
   {
     ProfScope ps(P, s, kCatDstCols, 2.0 * ts * S);
@@ -488,7 +488,7 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
   {
     ProfScope ps(P, s, kCatPcCols, 3.0 * ts * S);
     CK(launch_pc_cols<T>(P->Ldz, R, P1, P2, lamc, lamz, tw[P->Ldz], (int)plane - 1, n3, 1.0, P->kz,
-                         P->dpen, Kfac, s));
+                         P->dpen, Kfac, false, s));
   }
   {
     ProfScope ps(P, s, kCatDstCols, 4.0 * ts * S);
@@ -497,7 +497,7 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
   if (!w || P->Ldx != P->Lcx) {  // unfused (n1 = 1: convolution and sine lengths differ)
     {
       ProfScope ps(P, s, kCatPcRowsInv, 2.0 * ts * S + 9.0 * N);
-      CK(launch_pc_rows_inv<T>(P->Ldx, Q, R, P->mask, z, tw[P->Ldx], n1, rows, s));
+      CK(launch_pc_rows_inv<T>(P->Ldx, Q, R, P->mask, z, tw[P->Ldx], n1, rows, false, s));
     }
     return w ? matvec_impl(P, z, w, s, sub, theta) : RSFDE_OK;
   }
@@ -505,7 +505,7 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
     ProfScope ps(P, s, kCatPcInvMv, 2.0 * ts * S + 17.0 * N + (sub ? 8.0 * N : 0.0));
     CK(launch_pc_rows_inv_mv<T>(P->Ldx, Q, R, P->mask, z, P->t, tw[P->Ldx],
                                 P->tw64[P->Ldx], P->symx, -P->kx, P->dpen, sub, theta, n1, rows,
-                                s));
+                                false, s));
   }
   return matvec_cols3(P, z, w, s);
 }
@@ -537,17 +537,17 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
-      CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
+      CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 24.0 * S);
       CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
-                                P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 16.0 * S + 9.0 * N);
       CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mask, z, P->tw64[P->Ldx],
-                                    P->n1, P->n2, s));
+                                    P->n1, P->n2, true, s));
     }
     return RSFDE_OK;
   }
@@ -555,17 +555,17 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
-      CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
+      CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 12.0 * S);
       CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
-                               P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 8.0 * S + 9.0 * N);
       CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mask, z, P->tw32[P->Ldx],
-                                   P->n1, P->n2, s));
+                                   P->n1, P->n2, true, s));
     }
     return RSFDE_OK;
   }
@@ -600,35 +600,35 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
-      CK(launch_pc_rows_fwd<double>(P->Ldx, v, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, s));
+      CK(launch_pc_rows_fwd<double>(P->Ldx, v, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 24.0 * S);
       CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
-                                P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 16.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mask, z, P->t,
                                        P->tw64[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
-                                       sub, theta, P->n1, P->n2, s));
+                                       sub, theta, P->n1, P->n2, true, s));
     }
   } else {
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
-      CK(launch_pc_rows_fwd<float>(P->Ldx, v, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, s));
+      CK(launch_pc_rows_fwd<float>(P->Ldx, v, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 12.0 * S);
       CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
-                               P->n2, P->kx, P->ky, P->dpen, Kfac, s));
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 8.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mask, z, P->t,
                                       P->tw32[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
-                                      sub, theta, P->n1, P->n2, s));
+                                      sub, theta, P->n1, P->n2, true, s));
     }
   }
   {
@@ -1191,7 +1191,7 @@ int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) 
   double* q = nullptr;
   AL(q, slots);
   P->Q = q;
-  AL(q, slots);
+  AL(q, P->is3d ? slots : 2 * slots);
   P->P1 = q;
   AL(q, slots);
   P->P2 = q;
@@ -1340,7 +1340,10 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     P->Lgy = std::max(2, next_pow2(2L * n2 - 1));
   }
 
-  const size_t slots = (size_t)(n1 + 1) * (size_t)n2;
+  // Strip-tiled pass A/B/C intermediates: 8 values per tile of 2 rows x 4
+  // slots (at least the (n1 + 1) n2 of the natural layout; P1 holds the
+  // interleaved P1/P2 pairs, twice as many).
+  const size_t slots = (size_t)8 * (size_t)((n1 + 4) / 4) * (size_t)((n2 + 1) / 2);
   if ((rc = alloc_common(P, mask_dev, slots, s)) != RSFDE_OK) return fail(rc);
 
   // Matrix-vector symbols (unit kx, ky).
