@@ -151,6 +151,26 @@ __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* 
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }
 
+// Strip-tiled layout of a [rows][cols] array of intermediates: tiles of
+// [2 rows][4 columns], the tiles of one 4-column strip stored row pair after
+// row pair, the strips one after another.  A column pass that owns a strip
+// then reads and writes it contiguously; a row pass that owns a row pair moves
+// 64-byte pieces (FP64).  hp = row pairs per strip (ceil(rows / 2)); the
+// array holds 8 ceil(cols / 4) hp values.
+__device__ __forceinline__ size_t tile_index(int r, int c, int hp) {
+  return ((size_t)(c >> 2) * hp + (r >> 1)) * 8 + (r & 1) * 4 + (c & 3);
+}
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap the block
 // index so that consecutive logical tiles (adjacent column strips) run on the
 // same XCD and share its L2 lines.

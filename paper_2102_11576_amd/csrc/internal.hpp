@@ -54,16 +54,19 @@ struct RedWork {
 //   diag = (mode==0) ? 1 + dpen (1 - mask) : 0 (sub = NULL: no shift term),
 // where C_x is the Toeplitz matrix whose circulant embedding of length L has
 // the symbol `sym` (already divided by L, stored in register-position order).
+// tiled: out in the strip-tiled layout (tile_index; 8 ceil(n1/4) ceil(n2/2)
+// values), as the column pass reads t on two-dimensional plans.
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, double dpen, int mode, hipStream_t s,
-                          const double* sub = nullptr, double theta = 0.0);
+                          const double* sub = nullptr, double theta = 0.0, bool tiled = false);
 // Column pass: out = coef * (C_y z) + (mode==0 ? t : 0) on `batch` [n2][n1]
-// slices, slice b at offset b * bstride of z, t and out.
+// slices, slice b at offset b * bstride of z, t and out.  tiled (mode 0, one
+// slice): t in the strip-tiled layout.
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, int mode, hipStream_t s, int batch = 1,
-                          size_t bstride = 0);
+                          size_t bstride = 0, bool tiled = false);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
 // tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q and the
@@ -99,7 +102,8 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
 
 // Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
-// t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL).
+// t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL);
+// tiled: P1/P2 and t in the strip-tiled layout (t over n1 columns).
 template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,

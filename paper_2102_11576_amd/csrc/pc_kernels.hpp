@@ -32,21 +32,6 @@
 
 namespace rsfde {
 
-// Element of (row r, slot c) in the strip-tiled layout; hp = row pairs per
-// strip (ceil(rows / 2)).
-__device__ __forceinline__ size_t tile_index(int r, int c, int hp) {
-  return ((size_t)(c >> 2) * hp + (r >> 1)) * 8 + (r & 1) * 4 + (c & 3);
-}
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-  using type = double2;
-};
-template <>
-struct Vec2<float> {
-  using type = float2;
-};
 
 template <int L>
 struct PcCfg {
@@ -404,7 +389,8 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
 // takes a row pair through both: two inverse sweeps of pass C give z for rows
 // ra and rb (stored: the Krylov method keeps z, and the column pass reads it),
 // then one convolution on z_a + i z_b gives
-//   t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub.
+//   t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub
+// (t strip-tiled over n1 columns when TL, as the column pass reads it).
 // z is placed at positions 1..n1 of the convolution (where pass C leaves it),
 // a circular shift that the convolution carries to its output.
 // --------------------------------------------------------------------------
@@ -479,6 +465,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     reg[e].im *= sc;
   });
   fft_inverse<double, F>(reg, tau, tw64, my);
+  const int hp = (n2 + 1) >> 1;
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
@@ -487,13 +474,13 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
         const size_t i = (size_t)ra * n1 + (p - 1);
         double v = reg[e].re + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
         if (sub) v -= theta * sub[i];
-        t[i] = v;
+        t[TL ? tile_index(ra, p - 1, hp) : i] = v;
       }
       if (vb) {
         const size_t i = (size_t)rb * n1 + (p - 1);
         double v = reg[e].im + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
         if (sub) v -= theta * sub[i];
-        t[i] = v;
+        t[TL ? tile_index(rb, p - 1, hp) : i] = v;
       }
     }
   });

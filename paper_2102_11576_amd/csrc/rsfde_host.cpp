@@ -423,14 +423,15 @@ int matvec_impl(Plan* P, const double* x, double* y, hipStream_t s, const double
     }
     return matvec_cols3(P, x, y, s);
   }
-  {
+  {  // t strip-tiled (two-dimensional plans)
     ProfScope ps(P, s, kCatMvRows, (sub ? 25.0 : 17.0) * N);
     CK(launch_mv_rows(P->Lcx, x, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, -P->kx,
-                      P->dpen, 0, s, sub, theta));
+                      P->dpen, 0, s, sub, theta, true));
   }
   {
     ProfScope ps(P, s, kCatMvCols, 24.0 * N);
-    CK(launch_mv_cols(P->Lcy, x, P->t, y, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+    CK(launch_mv_cols(P->Lcy, x, P->t, y, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s, 1,
+                      0, true));
   }
   return RSFDE_OK;
 }
@@ -633,7 +634,8 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
   }
   {
     ProfScope ps(P, s, kCatMvCols, 24.0 * N);
-    CK(launch_mv_cols(P->Lcy, z, P->t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s));
+    CK(launch_mv_cols(P->Lcy, z, P->t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s, 1,
+                      0, true));
   }
   return RSFDE_OK;
 }
@@ -1185,7 +1187,10 @@ int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) 
   AL(P->Z, (size_t)max_restart * ld);
   AL(P->b, ld);
   AL(P->w, ld);
-  AL(P->t, ld);
+  // t: the matrix-vector intermediate, strip-tiled on two-dimensional plans
+  AL(P->t, P->is3d ? ld
+                   : std::max(ld, (size_t)8 * (size_t)((P->n1 + 3) / 4) *
+                                      (size_t)((P->n2 + 1) / 2)));
   AL(P->mu, ld);
   AL(P->pb, ld);
   double* q = nullptr;
