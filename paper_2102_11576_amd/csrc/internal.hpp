@@ -69,10 +69,10 @@ hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           size_t bstride = 0, bool tiled = false);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
-// tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q and the
-// interleaved P1/P2 pairs (array P1, P2 unused) are strip-tiled ([2 rows][4
-// slots] tiles, strip after strip; Q holds 4 ceil((n1+1)/4) ceil(n2/2) T
-// values, P1 twice as many).
+// tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q is
+// strip-tiled (tile_index; 8 ceil((n1+1)/4) ceil(n2/2) T values) and the
+// interleaved P1/P2 pairs (array P1, P2 unused) are in row segments
+// (pair_index; 2 W ceil((n1+1)/W) n2 T values, W = 64 / sizeof(T)).
 // Pass A: Q[r][slot] = raw x-sine sums of (sig * v) rows.
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q,
@@ -103,7 +103,7 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
 // Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
 // t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL);
-// tiled: P1/P2 and t in the strip-tiled layout (t over n1 columns).
+// tiled: P1/P2 pairs in row segments, t strip-tiled over n1 columns.
 template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,

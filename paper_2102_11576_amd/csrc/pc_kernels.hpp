@@ -20,17 +20,31 @@
 // output vectors are always FP64).
 //
 // Layout of the intermediates.  Natural (TL = false): Q, P1, P2 are
-// [rows][n+1] arrays.  Strip-tiled (TL = true, the two-dimensional plans):
-// tiles of [2 rows][4 slots], the tiles of one 4-slot strip stored row pair
-// after row pair and the strips one after another, with P1 and P2
-// interleaved (P1 at 2i, P2 at 2i + 1 of one array).  Pass B then reads and
-// writes whole strips contiguously, where the natural layout gives it 32-byte
-// pieces of rows 8 (n+1) bytes apart; the row passes move 64-byte pieces (a
-// row pair's 4 slots of Q, one row's P1/P2 pairs for 4 slots).
+// [rows][n+1] arrays.  Two-dimensional plans (TL = true): Q is strip-tiled
+// (tile_index: [2 rows][4 slots] tiles, strip after strip), and the P1/P2
+// pairs are interleaved in one array of row segments (pair_index).  Pass B
+// then reads Q in whole strips and writes whole 32-byte sectors, where the
+// natural layout gives it 32-byte pieces of rows 8 (n+1) bytes apart; pass A
+// writes 64-byte pieces of Q and pass C reads whole 128-byte lines of pairs.
 #pragma once
 #include "fft_common.hpp"
 
 namespace rsfde {
+
+// Row-segment layout of the interleaved (P1, P2) pairs: segments of
+// W = 64 / sizeof(T) slots per row (one 128-byte line of pairs), the
+// segments of one W-slot strip stored row after row, strip after strip.
+// Within every group of 4 slots the order is 0, 2, 1, 3: pass B's two column
+// pairs of a block finish slots (0, 2) in one sweep and (1, 3) in the other,
+// and each sweep then writes whole 32-byte sectors.  Returns the element of
+// P1 (P2 follows it); the array holds 2 W ceil(slots / W) rows values.
+template <typename T>
+__device__ __forceinline__ size_t pair_index(int r, int c, int rows) {
+  constexpr int W = 64 / (int)sizeof(T);
+  const int q = c % W;
+  const int pos = (q & ~3) | ((q & 1) << 1) | ((q >> 1) & 1);
+  return (((size_t)(c / W) * rows + r) * W + pos) * 2;
+}
 
 
 template <int L>
@@ -202,7 +216,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     const int p = F::pos(0, tau, e);
     if (valid && p >= 1 && p <= n2) {
       if constexpr (TL) {
-        *(V2*)(P1 + 2 * tile_index(p - 1, ca, hp)) = V2{reg[e].re, reg[e].im};
+        *(V2*)(P1 + pair_index<T>(p - 1, ca, n2)) = V2{reg[e].re, reg[e].im};
       } else {
         const size_t i = (size_t)(p - 1) * ld + ca;
         P1[i] = reg[e].re;
@@ -230,7 +244,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     const int p = F::pos(0, tau, e);
     if (valid && p >= 1 && p <= n2) {
       if constexpr (TL) {
-        *(V2*)(P1 + 2 * tile_index(p - 1, cb, hp)) = V2{reg[e].re, reg[e].im};
+        *(V2*)(P1 + pair_index<T>(p - 1, cb, n2)) = V2{reg[e].re, reg[e].im};
       } else {
         const size_t i = (size_t)(p - 1) * ld + cb;
         P1[i] = reg[e].re;
@@ -310,16 +324,16 @@ __device__ __forceinline__ void stage_slots(const T* p1, const T* p2, bool vr, i
   __syncthreads();
 }
 
-// The same from the strip-tiled layout (P1/P2 pairs of row r at
-// 2 tile_index(r, j, hp)): one 2-vector load per slot.
+// The same from the row-segment layout of the pairs (pair_index): one
+// 2-vector load per slot, a wavefront reading whole lines.
 template <typename T, class F>
-__device__ __forceinline__ void stage_slots_tiled(const T* pp, int r, bool vr, int ld, int hp,
+__device__ __forceinline__ void stage_slots_tiled(const T* pp, int r, bool vr, int ld, int rows,
                                                   int tau, T* my) {
   using V2 = typename Vec2<T>::type;
   static_for<F::PP / 2>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
     const int j = tau + k * F::TPF;  // < L/2 = ld
-    const V2 q = vr ? *(const V2*)(pp + 2 * tile_index(r, j, hp)) : V2{(T)0, (T)0};
+    const V2 q = vr ? *(const V2*)(pp + pair_index<T>(r, j, rows)) : V2{(T)0, (T)0};
     my[j] = q.x;
     my[ld + j] = q.y;
   });
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
   const int ld = n1 + 1;
   T* my = lds + b * lds_len(L);
   if constexpr (TL)
-    stage_slots_tiled<T, F>(P1, r, vr, ld, (n2 + 1) >> 1, tau, my);
+    stage_slots_tiled<T, F>(P1, r, vr, ld, n2, tau, my);
   else
     stage_slots<T, F>(P1 + (size_t)r * ld, P2 + (size_t)r * ld, vr, ld, tau, my);
   cpx<T> reg[F::PP];
@@ -428,7 +442,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     T* myT = reinterpret_cast<T*>(my);
     __syncthreads();  // the previous row's sweep may still read the region
     if constexpr (TL)
-      stage_slots_tiled<T, F>(P1h, r, vr, ld, (n2 + 1) >> 1, th, myT);
+      stage_slots_tiled<T, F>(P1h, r, vr, ld, n2, th, myT);
     else
       stage_slots<T, F>(P1h + (size_t)r * ld, P2h + (size_t)r * ld, vr, ld, th, myT);
     cpx<T> reg[F::PP];

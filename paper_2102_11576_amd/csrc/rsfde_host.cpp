@@ -1172,10 +1172,12 @@ namespace {
 
 // Workspaces every plan needs: the mask copy, Krylov basis V (restart + 1
 // vectors) and Z (restart), five work vectors, three (four in 3-D)
-// preconditioner intermediates of `slots` values (sized for FP64), the 3-D
+// preconditioner intermediates of `slots` values (sized for FP64; P1 of
+// p1_slots when that is larger), the 3-D
 // matrix-vector intermediate, reduction and s-step buffers, pinned status
 // words and events.  Enqueued on s.
-int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) {
+int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s,
+                 size_t p1_slots = 0) {
   const size_t N = P->N, ld = P->ldv;
   const int max_restart = P->max_restart;
 #define AL(ptr, cnt)                                              \
@@ -1196,7 +1198,7 @@ int alloc_common(Plan* P, const uint8_t* mask_dev, size_t slots, hipStream_t s) 
   double* q = nullptr;
   AL(q, slots);
   P->Q = q;
-  AL(q, P->is3d ? slots : 2 * slots);
+  AL(q, std::max(slots, p1_slots));
   P->P1 = q;
   AL(q, slots);
   P->P2 = q;
@@ -1345,11 +1347,13 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     P->Lgy = std::max(2, next_pow2(2L * n2 - 1));
   }
 
-  // Strip-tiled pass A/B/C intermediates: 8 values per tile of 2 rows x 4
-  // slots (at least the (n1 + 1) n2 of the natural layout; P1 holds the
-  // interleaved P1/P2 pairs, twice as many).
+  // Pass A/B/C intermediates: Q strip-tiled, 8 values per tile of 2 rows x 4
+  // slots (at least the (n1 + 1) n2 of the natural layout).  P1 holds the
+  // interleaved P1/P2 pairs in row segments of 8 (FP64) or 16 (FP32) slots.
   const size_t slots = (size_t)8 * (size_t)((n1 + 4) / 4) * (size_t)((n2 + 1) / 2);
-  if ((rc = alloc_common(P, mask_dev, slots, s)) != RSFDE_OK) return fail(rc);
+  const size_t pair_slots = (size_t)2 * (size_t)((n1 + 16) / 16 * 16) * (size_t)n2;
+  if ((rc = alloc_common(P, mask_dev, slots, s, std::max(2 * slots, pair_slots))) != RSFDE_OK)
+    return fail(rc);
 
   // Matrix-vector symbols (unit kx, ky).
   if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return fail(RSFDE_ENOMEM);
