@@ -6,7 +6,7 @@ matvec      : |w_gpu - w_ref|_inf <= 1e-13 * ||M||_inf ||z||_inf   (FFT rounding
               ~ eps log2(L) times that norm product; 1e-13 leaves ~40x headroom)
 precond FP64: |z_gpu - z_ref|_inf <= 1e-12 * ||z_ref||_inf          (orthogonal transforms)
 precond FP32: |z_gpu - z_ref|_inf <= 2e-5  * ||z_ref||_inf          (FP32 internals)
-step (FP64) : ||u_gpu - u_lu||_inf <= 1e-10 ||u_lu||_inf            (spec bound)
+step (FP64) : ||u_gpu - u_lu||_inf <= 1e-10 ||u_lu||_inf            (the parity bound of the step)
 """
 
 import numpy as np
