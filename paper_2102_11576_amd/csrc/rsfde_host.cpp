@@ -905,7 +905,7 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
 int gram_block(Plan* P, int nr, int nq, int ss, hipStream_t s) {
   const int32_t seq = ++P->gram_seq;
   {
-    ProfScope ps(P, s, kCatGram, 8.0 * (double)(nr + ss) * (double)P->N);
+    ProfScope ps(P, s, kCatGram, 8.0 * (double)nr * (double)P->N);  // [Q U] read once
     CK(launch_bgram(P->V, P->ldv, nr, nq, ss, P->N, P->gpart, P->gram_d, &P->hs_dev->gram_seq,
                     seq, &P->ks->gram_done, s));
   }
