@@ -24,7 +24,43 @@ constexpr int kGramThreads = 256;  // 4 wavefronts
 // and holds D[l/16 + 4i][l%16], i < 4.  The K index runs over elements: lane
 // group k takes elements base + 2k and base + 2k + 1 of each 8-element step
 // (one 16-byte load per row), the same mapping for A and B.
-template <int NT>
+// K chunks (c0, c0 + stride, ...) of 32 elements per row: lane group k4 loads
+// elements base + 8 q + 2 k4 and + 1, so that one load instruction reads 64
+// contiguous bytes of each of the wavefront's 16 rows (a mapping with 64-byte
+// strides between the lane groups measured 3.5-4.0 TB/s, a third below the
+// streaming kernels).  All K chunks' loads are issued before their MFMAs;
+// MFMA step (q, x|y) takes the same element of A and B.
+template <int NT, int K>
+__device__ __forceinline__ void gram_chunks(size_t c0, size_t stride, int k4, const double* brow,
+                                            bool bvalid, const double* const* arow,
+                                            const bool* avalid, v4d* acc) {
+  double2 b[K][4], a[K][NT][4];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const size_t e = (c0 + u * stride) * 32 + 2 * k4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      b[u][q] = bvalid ? reinterpret_cast<const double2*>(brow + e)[4 * q] : double2{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[u][t][q] =
+            avalid[t] ? reinterpret_cast<const double2*>(arow[t] + e)[4 * q] : double2{0.0, 0.0};
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].x, b[u][q].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].y, b[u][q].y, acc[t], 0, 0, 0);
+      }
+}
+
+// U2 chunks per loop iteration (2 where the registers allow: NT <= 2).
+template <int NT, int U2>
 __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict__ V, size_t ld,
                                                         int nr, int m1, int s, size_t N,
                                                         double* __restrict__ gpart) {
@@ -45,33 +81,13 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  // Chunks of 32 elements per row, in 4 steps q of 8: lane group k4 loads
-  // elements base + 8 q + 2 k4 and + 1, so that one load instruction reads 64
-  // contiguous bytes of each of the wavefront's 16 rows (a mapping with 64-byte
-  // strides between the lane groups measured 3.5-4.0 TB/s, a third below the
-  // streaming kernels).  MFMA step (q, x|y) takes the same element of A and B.
+  // Chunks of 32 elements, wave by wave over the grid (gram_chunks).
   const size_t nchunks = N / 32;
   const size_t gw = (size_t)gridDim.x * 4;
-  for (size_t ch = (size_t)blockIdx.x * 4 + wid; ch < nchunks; ch += gw) {
-    const size_t e = ch * 32 + 2 * k4;
-    double2 b[4], a[NT][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      b[q] = bvalid ? reinterpret_cast<const double2*>(brow + e)[4 * q] : double2{0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        a[t][q] =
-            avalid[t] ? reinterpret_cast<const double2*>(arow[t] + e)[4 * q] : double2{0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][q].x, b[q].x, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][q].y, b[q].y, acc[t], 0, 0, 0);
-      }
-  }
+  size_t ch = (size_t)blockIdx.x * 4 + wid;
+  for (; ch + (U2 - 1) * gw < nchunks; ch += U2 * gw)
+    gram_chunks<NT, U2>(ch, gw, k4, brow, bvalid, arow, avalid, acc);
+  for (; ch < nchunks; ch += gw) gram_chunks<NT, 1>(ch, gw, k4, brow, bvalid, arow, avalid, acc);
   // tail (N % 32 elements): block 0, wave 0 only
   if (blockIdx.x == 0 && wid == 0) {
     const size_t e0 = nchunks * 32 + 8 * k4;
@@ -216,12 +232,16 @@ hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_
   if (nb < 1) nb = 1;
   if (nb > kGramBlocks) nb = kGramBlocks;
   const int nt = (nr + 15) / 16;
+  // Two tiles with two chunks per iteration run at occupancy 3: half the
+  // blocks measured faster there (2047^2: 203 -> 191 us at 31 rows).
+  if (nt == 2 && nb > kGramBlocks / 2) nb = kGramBlocks / 2;
+  const dim3 g(nb), b(kGramThreads);
   switch (nt) {
-    case 1: hipLaunchKernelGGL(k_bgram<1>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
-    case 2: hipLaunchKernelGGL(k_bgram<2>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
-    case 3: hipLaunchKernelGGL(k_bgram<3>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
-    case 4: hipLaunchKernelGGL(k_bgram<4>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
-    case 5: hipLaunchKernelGGL(k_bgram<5>, dim3(nb), dim3(kGramThreads), 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 1: hipLaunchKernelGGL((k_bgram<1, 2>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 2: hipLaunchKernelGGL((k_bgram<2, 2>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 3: hipLaunchKernelGGL((k_bgram<3, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 4: hipLaunchKernelGGL((k_bgram<4, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 5: hipLaunchKernelGGL((k_bgram<5, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
     default: return hipErrorInvalidValue;
   }
   const int fb = (nr * s + kFinishThreads / 64 - 1) / (kFinishThreads / 64);
