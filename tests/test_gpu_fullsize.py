@@ -93,6 +93,10 @@ def test_full_4095_matvec_samples_precond_and_step():
         zp = pl.precond(_t(Z), precision="fp32").cpu().numpy().reshape(w.n2, w.n1)
         ref = O.precond_apply_fft(p, Z)
         assert np.linalg.norm(zp - ref) <= 1e-5 * np.linalg.norm(Z)
+        # FP64 internals at L = 8192 (one column pair per block, pairs in
+        # 8-slot row segments, where FP32 uses 16)
+        zp = pl.precond(_t(Z), precision="fp64").cpu().numpy().reshape(w.n2, w.n1)
+        assert np.linalg.norm(zp - ref) <= 1e-13 * np.linalg.norm(Z)
         u1, st = pl.step(_t(w.u0), None, w.f_kind, make_opts(w.restart, 100000, w.tol, "fp32"))
         u = u1.cpu().numpy().reshape(w.n2, w.n1)
     b = O.rhs(p, w.u0, w.f_kind)
