@@ -70,6 +70,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the HIP library is required; there is no fallback)")
+    # torch first: the library then binds to the HIP runtime that torch has
+    # loaded, and both see one device context.  Loaded before torch, it pulls
+    # in the system HIP runtime as a second copy in the process, which finds
+    # no device once torch's copy holds it.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     lib.rsfde_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,

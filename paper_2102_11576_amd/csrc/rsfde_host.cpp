@@ -1303,11 +1303,17 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   if (!h) return RSFDE_ENOMEM;
   Plan* P = &h->p;
   int rc = RSFDE_OK;
-  auto fail = [&](int code) {
+  // RSFDE_TRACE=1: a failed setup names its line and the last HIP error.
+  const char* trace_env = std::getenv("RSFDE_TRACE");
+  const bool tr_on = trace_env && trace_env[0] == '1';
+  auto failx = [&](int line, int code) {
+    if (tr_on)
+      std::fprintf(stderr, "[rsfde] setup failed at line %d (%d): last HIP error %s\n", line, code,
+                   hipGetErrorString(hipGetLastError()));
     delete h;
     return code;
   };
-  if (hipGetDevice(&P->dev) != hipSuccess) return fail(RSFDE_EHIP);
+  if (hipGetDevice(&P->dev) != hipSuccess) return failx(__LINE__, RSFDE_EHIP);
   hipStream_t s = (hipStream_t)stream;
   P->s0 = s;
   P->n1 = n1;
@@ -1353,13 +1359,13 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
   const size_t slots = (size_t)8 * (size_t)((n1 + 4) / 4) * (size_t)((n2 + 1) / 2);
   const size_t pair_slots = (size_t)2 * (size_t)((n1 + 16) / 16 * 16) * (size_t)n2;
   if ((rc = alloc_common(P, mask_dev, slots, s, std::max(2 * slots, pair_slots))) != RSFDE_OK)
-    return fail(rc);
+    return failx(__LINE__, rc);
 
   // Matrix-vector symbols (unit kx, ky).
-  if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return fail(RSFDE_ENOMEM);
-  if (upload(P, &P->symy, conv_symbol_pos(ty, P->Lcy), s) != hipSuccess) return fail(RSFDE_ENOMEM);
+  if (upload(P, &P->symx, conv_symbol_pos(tx, P->Lcx), s) != hipSuccess) return failx(__LINE__, RSFDE_ENOMEM);
+  if (upload(P, &P->symy, conv_symbol_pos(ty, P->Lcy), s) != hipSuccess) return failx(__LINE__, RSFDE_ENOMEM);
   for (int L : {P->Lcx, P->Lcy, P->Ldx, P->Ldy, P->Lgx, P->Lgy})
-    if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
+    if (ensure_twiddles(P, L, s) != hipSuccess) return failx(__LINE__, RSFDE_ENOMEM);
 
   // Preconditioner tables (Section 4.1), in the layouts of the three passes.
   if (P->Ldx && P->Ldy) {
@@ -1368,12 +1374,12 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     std::vector<float> lamx_f(lamx.begin(), lamx.end()), lamy_f(lamy.begin(), lamy.end());
     if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
         upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess)
-      return fail(RSFDE_ENOMEM);
+      return failx(__LINE__, RSFDE_ENOMEM);
   }
   if (P->Lgx) {  // chirp-form tables
     const std::vector<double> lx = tau_eigs(tx), ly = tau_eigs(ty);
     if (upload(P, &P->lamx_n, lx, s) != hipSuccess || upload(P, &P->lamy_n, ly, s) != hipSuccess)
-      return fail(RSFDE_ENOMEM);
+      return failx(__LINE__, RSFDE_ENOMEM);
     struct Dir { int n, L; void **ch, **kh; };
     for (Dir d : {Dir{n1, P->Lgx, P->chx, P->khx}, Dir{n2, P->Lgy, P->chy, P->khy}}) {
       std::vector<double> ch, kh;
@@ -1383,7 +1389,7 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
       float *c = nullptr, *e = nullptr;
       if (upload(P, &a, ch, s) != hipSuccess || upload(P, &b, kh, s) != hipSuccess ||
           upload(P, &c, chf, s) != hipSuccess || upload(P, &e, khf, s) != hipSuccess)
-        return fail(RSFDE_ENOMEM);
+        return failx(__LINE__, RSFDE_ENOMEM);
       d.ch[0] = a;
       d.kh[0] = b;
       d.ch[1] = c;
@@ -1405,7 +1411,7 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     if (upload(P, &sxd, sx, s) != hipSuccess || upload(P, &syd, sy, s) != hipSuccess ||
         upload(P, &sxld, sxl, s) != hipSuccess || upload(P, &syld, syl, s) != hipSuccess ||
         upload(P, &P->lamx_nat, lxn, s) != hipSuccess || upload(P, &P->lamy_nat, lyn, s) != hipSuccess)
-      return fail(RSFDE_ENOMEM);
+      return failx(__LINE__, RSFDE_ENOMEM);
     P->Sx16 = (__bf16*)sxd;
     P->Sy16 = (__bf16*)syd;
     P->Sx16lo = (__bf16*)sxld;
@@ -1413,9 +1419,9 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     const size_t pp = (size_t)P->n1p * (size_t)P->n2p;
     if (P->dalloc(&P->A1T, 2 * pp) != hipSuccess || P->dalloc(&P->R12T, 2 * pp) != hipSuccess ||
         P->dalloc(&P->G, 2 * pp) != hipSuccess)
-      return fail(RSFDE_ENOMEM);
+      return failx(__LINE__, RSFDE_ENOMEM);
   }
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(RSFDE_EHIP);
+  if (hipStreamSynchronize(s) != hipSuccess) return failx(__LINE__, RSFDE_EHIP);
   (void)rc;
   *out = h;
   return RSFDE_OK;

@@ -267,3 +267,21 @@ def test_reorthogonalisation_option(precision, reorth):
         u = u.cpu().numpy().reshape(w.n2, w.n1)
     err = np.abs(u - ref).max() / np.abs(ref).max()
     assert err <= 1e-10, (err, iters)
+
+
+def test_package_imported_before_torch():
+    """A script that imports the package before torch still finds the device:
+    the package loads torch before the HIP library, so both use one HIP
+    runtime (with the library loaded first, setup found no device)."""
+    import subprocess
+    import sys
+    from pathlib import Path
+    code = ("import paper_2102_11576_amd as m\n"
+            "from workloads.configs import make_config\n"
+            "w = make_config('c1')\n"
+            "with m.RsfdePlan.from_workload(w) as pl:\n"
+            "    print('setup ok')\n")
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0 and "setup ok" in r.stdout, r.stderr[-2000:]
