@@ -163,10 +163,15 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
   const int tid = threadIdx.x;
   const int b = tid % C::BC, tau = tid / C::BC;
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
-  const int cp = strip * C::BC + b;
-  const int ca = 2 * cp, cb = 2 * cp + 1;
+  // Column pair of FFT b.  Tiled: (2c, 2c+1), adjacent in one tile row.
+  // Natural: (base + b, base + b + BC) of the block's 2 BC columns, so that
+  // each inverse sweep writes BC adjacent columns of a row (with (2c, 2c+1)
+  // every sweep wrote every other column and half-written lines doubled the
+  // write traffic).
+  const int ca = TL ? 2 * (strip * C::BC + b) : 2 * C::BC * strip + b;
+  const int cb = TL ? ca + 1 : ca + C::BC;
   const int ld = n1 + 1, hp = (n2 + 1) >> 1;
-  const bool valid = cb < ld;  // n1 + 1 is even: both or neither
+  const bool va = ca < ld, vb = cb < ld;  // tiled: ld and ca even, both or neither
   using V2 = typename Vec2<T>::type;
   cpx<T> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
@@ -180,23 +185,23 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
       row = L - p - 1;
       sgn = (T)-1;
     }
-    const bool ok = valid && row >= 0;
     if constexpr (TL) {
       // ca is even: (ca, cb) are adjacent elements of one tile row
+      const bool ok = vb && row >= 0;
       const V2 q = ok ? *(const V2*)(Q + tile_index(row, ca, hp)) : V2{(T)0, (T)0};
       reg[e].re = sgn * q.x;
       reg[e].im = sgn * q.y;
     } else {
-      reg[e].re = ok ? sgn * Q[(size_t)row * ld + ca] : (T)0;
-      reg[e].im = ok ? sgn * Q[(size_t)row * ld + cb] : (T)0;
+      reg[e].re = (va && row >= 0) ? sgn * Q[(size_t)row * ld + ca] : (T)0;
+      reg[e].im = (vb && row >= 0) ? sgn * Q[(size_t)row * ld + cb] : (T)0;
     }
   });
   T* my = lds + b;  // regions interleaved (stride BC)
   // (no register materialisation between the sweeps here: it measured slower)
   fft_forward<T, F, false, C::BC>(reg, tau, tw, my);
   // spectrum = 2 rho_b - 2i rho_a; keep rho_b for the second column
-  const T lxa = valid ? kx * lamx_slot[ca] : (T)0;
-  const T lxb = valid ? kx * lamx_slot[cb] : (T)0;
+  const T lxa = va ? kx * lamx_slot[ca] : (T)0;
+  const T lxb = vb ? kx * lamx_slot[cb] : (T)0;
   T rho_b[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
-    if (valid && p >= 1 && p <= n2) {
+    if (va && p >= 1 && p <= n2) {
       if constexpr (TL) {
         *(V2*)(P1 + pair_index<T>(p - 1, ca, n2)) = V2{reg[e].re, reg[e].im};
       } else {
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
-    if (valid && p >= 1 && p <= n2) {
+    if (vb && p >= 1 && p <= n2) {
       if constexpr (TL) {
         *(V2*)(P1 + pair_index<T>(p - 1, cb, n2)) = V2{reg[e].re, reg[e].im};
       } else {
