@@ -106,6 +106,10 @@ def parse():
                     default="march",
                     help="kernels: repeat each operator in isolation (for counter profiles)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed marches of the headline (the median is reported)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the c1 / c2 / c5 legs")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-one-vector", action="store_true",
                     help="skip the one-vector-per-step comparison march (profiling runs)")
@@ -150,45 +154,62 @@ def kernel_mode(args):
 
 
 def cpu_baseline(w, gpu_iters_per_step):
-    """The oracle as it stands (dense-free O2 operators: scipy FFT Toeplitz
-    products and DST-I, MGS GMRES) on a bounded sample of the same workload:
-    the first 2 and the first 8 inner iterations of step 1.  The difference
-    gives the cost of one inner iteration; the 2-iteration run minus two
-    iterations gives the fixed per-step cost (right-hand side, residuals,
-    update).  Scaled to unknown*timesteps/s with the GPU run's mean iterations
-    per step (same algorithm and stopping rule)."""
+    """The oracle as it stands, timed on this host's cores on a bounded sample
+    of the same workload.
+
+    Main figure (c3 at its full size): the right-hand side and one whole
+    restart cycle (GMRES(30): inner iterations j = 0..29 with their growing
+    modified Gram-Schmidt cost, the update and the true residual) of step 1,
+    with the oracle's fast operators (scipy FFT Toeplitz products and the scipy
+    DST-I preconditioner).  Every cycle of a step has this j-profile, so a step
+    of K inner iterations costs (set-up) + (K / 30) cycles; K is the GPU run's
+    mean (same algorithm and stopping rule).  Also reported: the dense-LU
+    oracle (forming M, one LU factorisation, 16 solves) on the 63^2 shape of
+    c1, timed whole."""
     import numpy as np
     import oracle as O
+    from workloads.configs import make_config
 
     p = O.problem_from_workload(w)
     lam = O.tau_eigs_xy(p)
     A = lambda V: O.matvec_fast(p, V)  # noqa: E731
     Pi = lambda V: O.precond_apply_fft(p, V, lam)  # noqa: E731
-    times = {}
-    for k in (2, 8):
-        t0 = time.perf_counter()
-        b = O.rhs(p, w.u0, w.f_kind)
-        O.gmres(A, b, w.u0, w.restart, w.tol, k, Pi, "right")
-        times[k] = time.perf_counter() - t0
-    t_it = (times[8] - times[2]) / 6.0
-    fixed = max(times[2] - 2 * t_it, 0.0)
-    t_step = fixed + gpu_iters_per_step * t_it
-    cores = os.cpu_count()
+    t0 = time.perf_counter()
+    b = O.rhs(p, w.u0, w.f_kind)
+    t_rhs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its, _ = O.gmres(A, b, w.u0, w.restart, 1e-300, w.restart, Pi, "right")
+    t_cycle = time.perf_counter() - t0
+    t_step = t_rhs + (gpu_iters_per_step / w.restart) * t_cycle
+    # dense LU on the c1 shape (the survey's O1 tier), whole
+    w1 = make_config("c1")
+    p1 = O.problem_from_workload(w1)
+    t0 = time.perf_counter()
+    O.march_lu(p1, w1.u0, w1.m, w1.f_kind)
+    t_lu = time.perf_counter() - t0
+    blas = None
     try:
         from threadpoolctl import threadpool_info
-        blas = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
-        cores = max(int(blas), 1) if blas else cores
+        blas = max((int(i.get("num_threads", 1)) for i in threadpool_info()), default=None)
     except Exception:
         pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = os.cpu_count()
     return {
         "value": w.N / t_step,
         "unit": "unknown·timesteps/s",
-        "cores": cores,
+        "cores": affinity,
         "kind": "oracle",
-        "sample": (f"step 1 of the same {w.n1}x{w.n2} workload: oracle GMRES (scipy FFT Toeplitz "
-                   f"matvec, scipy DST-I preconditioner, MGS) for 2 and 8 inner iterations "
-                   f"({times[2]:.1f}s, {times[8]:.1f}s): {t_it:.3f}s/iteration + {fixed:.2f}s/step, "
-                   f"scaled by {gpu_iters_per_step:.1f} iterations/step"),
+        "sample": (f"{w.n1}x{w.n2} workload, step 1: right-hand side ({t_rhs:.2f} s) and one whole "
+                   f"GMRES({w.restart}) restart cycle ({its} inner iterations, MGS, scipy FFT "
+                   f"Toeplitz matvec, scipy DST-I preconditioner: {t_cycle:.1f} s); a step = "
+                   f"set-up + {gpu_iters_per_step:.1f}/{w.restart} cycles (the GPU's mean "
+                   f"iterations per step)"),
+        "threads": {"scipy_fft_workers": os.cpu_count(), "blas": blas, "affinity_cpus": affinity},
+        "dense_lu_c1": {"value": w1.N * w1.m / t_lu, "seconds": t_lu,
+                        "sample": f"c1 63x63, 16 steps: dense M, one LU factorisation, 16 solves"},
     }
 
 
@@ -250,6 +271,105 @@ def adjoint_rate(log, sstep=0):
             an = float(torch.dot(g0, dut)) + gkx * dkx + gky * dky
             errs.append(abs(fd - an) / abs(an))
         res["fd_rel_err_2_dirs"] = errs
+    return res
+
+
+def configs_rates(log, sstep=10):
+    """The other configurations of the benchmark family, each marched whole.
+
+    c1 (63^2 disk, 16 steps, GMRES(20) tol 1e-10, one Arnoldi vector per step:
+    the grid is below the s-step floor of 4096 unknowns): latency-bound, so
+    microseconds per inner iteration are reported.  c2 (1023^2 ellipse, 64
+    steps, GMRES(30) tol 1e-8, s-step): throughput.  c5 (4095^2 hexagon, 16
+    steps, FP32 preconditioner inside FGMRES(20) tol 1e-8, s-step): forward
+    march, then one backward pass (checkpointed forward + adjoint sweep, FP32
+    preconditioner in both) for the gradient of L = ||u(T)||^2 with respect to
+    u0, kx and ky, checked by central differences (h = 1e-6, tol 1e-12) on two
+    seeded directions."""
+    import numpy as np
+    import torch
+    from paper_2102_11576_amd import RsfdePlan, make_opts
+    from paper_2102_11576_amd.autograd import RsfdeMarch
+    from workloads.configs import make_config, fd_direction
+    dev = torch.device("cuda:0")
+    res = {}
+
+    def march(pl, w, opts, reps):
+        u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+        pl.march(u0, min(2, w.m), w.f_kind, opts)
+        torch.cuda.synchronize()
+        ts, its = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, its, _ = pl.march(u0, w.m, w.f_kind, opts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), its
+
+    w = make_config("c1")
+    with RsfdePlan.from_workload(w, device=dev) as pl:
+        t, its = march(pl, w, make_opts(w.restart, 100000, w.tol), 5)
+    res["c1"] = {"workload": "c1: 63x63 disk r=0.45, alpha=(1.5,1.7), 16 steps, GMRES(20) tol 1e-10, "
+                             "one vector per step", "unknown_timesteps_per_s": w.N * w.m / t,
+                 "us_per_iteration": 1e6 * t / sum(its), "gmres_iters_per_step": float(np.mean(its)),
+                 "ms_per_step": 1e3 * t / w.m, "timing": "median of 5 whole marches"}
+    log(f"c1: {res['c1']['us_per_iteration']:.1f} us/iteration, {np.mean(its):.1f} iterations/step")
+
+    w = make_config("c2")
+    with RsfdePlan.from_workload(w, device=dev) as pl:
+        t, its = march(pl, w, make_opts(w.restart, 100000, w.tol, sstep=sstep), 5)
+    res["c2"] = {"workload": "c2: 1023x1023 ellipse .45/.30, alpha=(1.2,1.8), k=(1,0.5), 64 steps, "
+                             f"GMRES(30) tol 1e-8, s-step (s={sstep})",
+                 "unknown_timesteps_per_s": w.N * w.m / t, "ms_per_step": 1e3 * t / w.m,
+                 "gmres_iters_per_step": float(np.mean(its)), "timing": "median of 5 whole marches"}
+    log(f"c2: {res['c2']['unknown_timesteps_per_s']:.3e} unknown*timesteps/s, {np.mean(its):.1f} it/step")
+
+    w = make_config("c5")
+    opts = make_opts(w.restart, 100000, w.tol, "fp32", sstep=sstep)
+    with RsfdePlan.from_workload(w, device=dev) as pl:
+        t, its = march(pl, w, opts, 1)
+        r5 = {"workload": "c5: 4095x4095 hexagon R=0.45, alpha=(1.4,1.75), 16 steps, f=u-u^3, "
+                          f"FP32 preconditioner in FGMRES(20) tol 1e-8, s-step (s={sstep})",
+              "unknown_timesteps_per_s": w.N * w.m / t, "ms_per_step": 1e3 * t / w.m,
+              "gmres_iters_per_step": float(np.mean(its))}
+        log(f"c5 forward: {r5['unknown_timesteps_per_s']:.3e} unknown*timesteps/s")
+        u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+
+        def grad(op):
+            x0 = u0.clone().requires_grad_(True)
+            kx = torch.tensor(w.kx, dtype=torch.float64, device=dev, requires_grad=True)
+            ky = torch.tensor(w.ky, dtype=torch.float64, device=dev, requires_grad=True)
+            uT = RsfdeMarch.apply(x0, kx, ky, pl, w.m, w.f_kind, op)
+            (uT * uT).sum().backward()
+            return x0.grad, float(kx.grad), float(ky.grad)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grad(opts)
+        torch.cuda.synchronize()
+        r5["backward_pass_s"] = time.perf_counter() - t0
+        log(f"c5 gradient (checkpointed forward + adjoint sweep): {r5['backward_pass_s']:.2f} s")
+        tight = make_opts(w.restart, 100000, 1e-12, "fp32", sstep=sstep)
+        g0, gkx, gky = grad(tight)
+
+        def loss(uu0, kx, ky):
+            pl.set_coeffs(kx, ky)
+            uT = pl.march(uu0, w.m, w.f_kind, tight)[0]
+            return float((uT * uT).sum())
+        errs = []
+        for i in range(2):
+            du, dkx, dky = fd_direction(w.u0.shape, i)
+            dut = torch.as_tensor(du, device=dev).reshape(-1)
+            h = 1e-6
+            fd = (loss(u0 + h * dut, w.kx + h * dkx, w.ky + h * dky)
+                  - loss(u0 - h * dut, w.kx - h * dkx, w.ky - h * dky)) / (2 * h)
+            an = float(torch.dot(g0, dut)) + gkx * dkx + gky * dky
+            errs.append(abs(fd - an) / abs(an))
+        pl.set_coeffs(w.kx, w.ky)
+        r5["fd_rel_err_2_dirs"] = errs
+        r5["loss"] = "||u(T)||^2; gradient w.r.t. u0 (full field), kx, ky"
+        log(f"c5 FD check: {errs}")
+    res["c5"] = r5
     return res
 
 
@@ -525,11 +645,17 @@ def main():
             L.rsfde_profile(plan.handle, False)
         return u, iters, dt, prof
 
-    log(f"workload {w.name} {w.n1}x{w.n2}, timing {K} steps after {W} warm-up steps")
-    u64, it64, t64, _ = timed_march("fp64", K)
+    log(f"workload {w.name} {w.n1}x{w.n2}, timing {K} steps after {W} warm-up steps, "
+        f"{args.repeats} runs")
+    runs = []
+    for r in range(max(1, args.repeats)):
+        u64, it64, t, _ = timed_march("fp64", K)
+        runs.append(t)
+        log(f"run {r + 1}: {1e3 * t / K:.2f} ms/step")
+    t64 = float(np.median(runs))
     value = w.N * K / t64
     form = f"s-step (s={args.sstep})" if args.sstep >= 2 else "one vector per step"
-    log(f"fp64, {form}: {1e3 * t64 / K:.2f} ms/step, {np.mean(it64):.1f} iterations/step")
+    log(f"fp64, {form}: {1e3 * t64 / K:.2f} ms/step (median), {np.mean(it64):.1f} iterations/step")
     out = {
         "metric": METRIC,
         "value": value,
@@ -551,6 +677,8 @@ def main():
             "preconditioner": "fp64",
             "gmres_form": form,
         },
+        "timing": {"statistic": f"median of {len(runs)} timed marches of {K} steps",
+                   "ms_per_step_runs": [1e3 * t / K for t in runs]},
         "gmres_iters_per_step": float(np.mean(it64)),
         "gmres_iters": it64,
     }
@@ -566,10 +694,17 @@ def main():
         u32, it32, t32, _ = timed_march("fp32", K)
         log(f"fp32 preconditioner: {1e3 * t32 / K:.2f} ms/step, {np.mean(it32):.1f} iterations/step")
         d = float((u32 - u64).abs().max() / u64.abs().max())
-        # BF16 preconditioner: bounded to the first KB steps.  At this stiffness the
-        # flexible GMRES stalls from step 3 on (BF16 rounding of the preconditioned
-        # vector is amplified by ||M|| ~ 1e5), so the full march is
-        # not run here.
+        # FP64 reference at tol 1e-12: both tol-1e-8 results against it
+        opts_t = make_opts(w.restart, 100000, 1e-12, "fp64", sstep=args.sstep)
+        u_t, it_t, _ = plan.march(u0, K, w.f_kind, opts_t)
+        torch.cuda.synchronize()
+        d64_t = float((u64 - u_t).abs().max() / u_t.abs().max())
+        d32_t = float((u32 - u_t).abs().max() / u_t.abs().max())
+        log(f"vs FP64 at tol 1e-12: fp64 {d64_t:.2e}, fp32 {d32_t:.2e}")
+        # BF16 preconditioner: not supported at this stiffness.  Flexible GMRES
+        # stalls from step 3 on (the BF16 rounding of each preconditioned
+        # vector, about 6e-3 relative, is amplified by ||M|| ~ 1e5 in the next
+        # product); the first KB steps converge and are reported as such.
         KB = min(2, K)
         u64b, _, _, _ = timed_march("fp64", KB, sstep=0)
         ub, itb, tb, profb = timed_march("bf16", KB, profile=not args.no_profile, sstep=0)
@@ -578,11 +713,17 @@ def main():
         db = float((ub - u64b).abs().max() / u64b.abs().max())
         out["mixed"] = {
             "fp32": {"value": w.N * K / t32, "ms_per_step": 1e3 * t32 / K, "steps": K,
-                     "gmres_iters_per_step": float(np.mean(it32)), "rel_err_inf_vs_fp64": d},
-            "bf16": {"value": w.N * KB / tb, "ms_per_step": 1e3 * tb / KB, "steps": KB,
-                     "gmres_iters_per_step": float(np.mean(itb)), "rel_err_inf_vs_fp64": db,
-                     "note": "first steps only: from step 3 on flexible GMRES stalls at this "
-                             "stiffness with a BF16 preconditioner"},
+                     "gmres_iters_per_step": float(np.mean(it32)), "rel_err_inf_vs_fp64": d,
+                     "rel_err_inf_vs_fp64_tol_1e-12": d32_t},
+            "fp64_rel_err_inf_vs_fp64_tol_1e-12": d64_t,
+            "fp64_tol_1e-12_iters_per_step": float(np.mean(it_t)),
+            "bf16": {"supported": False,
+                     "reason": "flexible GMRES stalls from step 3 on at this stiffness: the BF16 "
+                               "rounding of each preconditioned vector (about 6e-3 relative) is "
+                               "amplified by ||M|| ~ 1e5 in the next matrix-vector product",
+                     "first_steps": {"value": w.N * KB / tb, "ms_per_step": 1e3 * tb / KB,
+                                     "steps": KB, "gmres_iters_per_step": float(np.mean(itb)),
+                                     "rel_err_inf_vs_fp64": db}},
         }
         if profb and "pc_gemm_bf16" in profb:
             n_l, ms_l, _ = profb["pc_gemm_bf16"]
@@ -591,7 +732,7 @@ def main():
             # products: 2*2*n1p*n2p*(n1p + n2p)  (20 n^3 per apply for n1 = n2)
             flops = 10.0 * n1p * n2p * (n1p + n2p)
             tfs = flops / (ms_l / n_l * 1e-3) / 1e12
-            out["mixed"]["bf16"]["mfma_roofline"] = {
+            out["mixed"]["bf16"]["first_steps"]["mfma_roofline"] = {
                 "kernel": "pc_gemm_bf16", "bound": "mfma", "achieved": tfs, "peak": 2500.0,
                 "unit": "TFLOP/s", "frac": tfs / 2500.0, "avg_apply_us": 1e3 * ms_l / n_l,
                 "flops_per_apply": flops}
@@ -611,12 +752,16 @@ def main():
         if fl is not None:
             # FFT passes: bound by FP64 vector issue and LDS exchanges, not by HBM
             tfs = fl / (ms / n * 1e-3) / 1e12
+            traf = traffic_for(name, by / n)
             out["roofline"] = {"bound": "alu", "kernel": name, "achieved": tfs,
                                "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s",
                                "frac": tfs / FP64_VALU_PEAK_TFS,
-                               "traffic": traffic_for(name, by / n),
+                               "traffic": traf,
                                "flops_per_launch": fl, "alg_bytes_per_launch": by / n,
-                               "hbm_GBs_algorithmic": ach, "avg_launch_us": 1e3 * ms / n}
+                               "hbm_GBs_algorithmic": ach, "hbm_frac_algorithmic": ach / HBM_PEAK_GBS,
+                               "hbm_frac_counters": (traf / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                     if traf else None),
+                               "avg_launch_us": 1e3 * ms / n}
         else:
             out["roofline"] = {"bound": "hbm", "kernel": name, "achieved": ach,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
@@ -626,6 +771,10 @@ def main():
             flk = fft_flops(nm, w.n1, w.n2)
             if flk is not None and kv["total_ms"] > 0:
                 kv["fp64_TFs"] = flk * kv["launches"] / (kv["total_ms"] * 1e-3) / 1e12
+                kv["frac_of_fp64_valu_peak"] = kv["fp64_TFs"] / FP64_VALU_PEAK_TFS
+                trk = traffic_for(nm, prof[nm][2] / kv["launches"])
+                if trk:
+                    kv["hbm_frac_counters"] = trk / (kv["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
         out["kernels"] = kernels
         out["profiled_ms_per_step"] = 1e3 * tprof / K
 
@@ -634,6 +783,9 @@ def main():
 
     if not args.no_ensemble:
         out["ensemble"] = ensemble_rate(log, args.sstep)
+
+    if not args.no_configs:
+        out["configs"] = configs_rates(log, args.sstep)
 
     if not args.no_three_d:
         out["three_d"] = three_d_rate(log, args.sstep)

@@ -82,8 +82,8 @@ typedef struct {
   double tol;        /* relative tolerance > 0 of the stopping rule of `side` */
   int32_t precision; /* RSFDE_FP64 / RSFDE_FP32 / RSFDE_BF16: preconditioner arithmetic */
   int32_t precond;   /* RSFDE_PRECOND_TAU or RSFDE_PRECOND_NONE */
-  int32_t reorth;    /* Gram-Schmidt passes: 1 = two (CGS2), -1 = one (CGS),
-                        0 = default: two with the BF16 preconditioner, else one */
+  int32_t reorth;    /* Gram-Schmidt passes of the one-vector form: 0 (default) or
+                        1 = two (CGS2), -1 = one (CGS) */
   int32_t side;      /* RSFDE_RIGHT (default) or RSFDE_LEFT; with RSFDE_PRECOND_NONE
                         both are plain GMRES */
   int32_t sstep;     /* 0 or 1: one Arnoldi vector per step (classical Gram-Schmidt).

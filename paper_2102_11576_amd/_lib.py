@@ -150,16 +150,25 @@ def _raise(rc, where):
         raise RsfdeError(rc, where)
 
 
+DEFAULT_SSTEP = 10
+
+
 def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0,
-              side="right", sstep=0):
-    """reorth: 1 = two Gram-Schmidt passes, -1 = one, 0 = two only with BF16.
-    side: "right" (flexible GMRES, true-residual stop) or "left" (the stopping
-    rule of the paper's experiments).  sstep: 0/1 one Arnoldi vector per step,
-    s >= 2 the s-step block form."""
+              side="right", sstep=None):
+    """reorth: 0 or 1 = two Gram-Schmidt passes (CGS2), -1 = one (one-vector
+    form only).  side: "right" (flexible GMRES, true-residual stop) or "left"
+    (the stopping rule of the paper's experiments).  sstep: 0/1 one Arnoldi
+    vector per step, s >= 2 the s-step block form; None (default) picks the
+    s-step form with s = 10 where it is supported (right side, sine-transform
+    preconditioner in FP64 or FP32; the library itself takes the one-vector
+    form on grids below 4096 unknowns) and the one-vector form elsewhere."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
         if isinstance(precond, str) else int(precond)
     sd = {"right": RSFDE_RIGHT, "left": RSFDE_LEFT}[side] if isinstance(side, str) else int(side)
+    if sstep is None:
+        ok = sd == RSFDE_RIGHT and pc == RSFDE_PRECOND_TAU and p in (RSFDE_FP64, RSFDE_FP32)
+        sstep = DEFAULT_SSTEP if ok and int(restart) + 1 + DEFAULT_SSTEP <= 80 else 0
     return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), sd,
                              int(sstep))
 

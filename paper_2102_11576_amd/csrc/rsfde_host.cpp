@@ -21,19 +21,14 @@
 
 #include "../../include/rsfde.h"
 #include "internal.hpp"
+#include "tables.hpp"
 
 namespace rsfde {
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846264338327950288;
+using namespace tables;
 
-bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
-int next_pow2(long v) {
-  int p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
 
 struct DeviceGuard {
   int prev = -1;
@@ -54,17 +49,6 @@ struct DeviceGuard {
     if (e_ != hipSuccess) return RSFDE_EHIP;       \
   } while (0)
 
-// cos(2 pi k / L) for k < L, with exact integer argument reduction by the caller.
-std::vector<double> cos_table(int L) {
-  std::vector<double> c(L);
-  for (int k = 0; k < L; ++k) {
-    // reduce to the first octant-free form: angle = 2 pi k / L in [0, 2 pi)
-    c[k] = std::cos(2.0 * kPi * (double)k / (double)L);
-  }
-  // make the symmetric values exactly symmetric
-  for (int k = 1; k < L; ++k) c[L - k] = c[k] = (k <= L - k) ? c[k] : c[L - k];
-  return c;
-}
 
 }  // namespace
 
@@ -223,35 +207,7 @@ struct ProfScope {
   }
 };
 
-// First column of the unit-coefficient Toeplitz matrix c * G_n^(alpha) (G).
-std::vector<double> toeplitz_col(double alpha, int n, double c) {
-  std::vector<double> g(n + 2);
-  g[0] = 1.0;
-  for (int l = 1; l < n + 2; ++l) g[l] = (1.0 - (alpha + 1.0) / l) * g[l - 1];
-  std::vector<double> t(n);
-  t[0] = 2.0 * g[1];
-  if (n > 1) t[1] = g[0] + g[2];
-  for (int k = 2; k < n; ++k) t[k] = g[k + 1];
-  for (auto& v : t) v *= c;
-  return t;
-}
 
-// Symbol of the circulant embedding of length L (L >= 2n - 1) of the symmetric
-// Toeplitz matrix with first column t, divided by L, in the register-position
-// order of the FFT of length L.
-std::vector<double> conv_symbol_pos(const std::vector<double>& t, int L) {
-  const int n = (int)t.size();
-  std::vector<double> ct = cos_table(L), chat(L);
-  for (int f = 0; f < L; ++f) {
-    double s = t[0];
-    for (int j = 1; j < n; ++j) s += 2.0 * t[j] * ct[(int)(((long long)j * f) % L)];
-    chat[f] = s;
-  }
-  const int P = fft_pts(L);
-  std::vector<double> out(L);
-  for (int p = 0; p < L; ++p) out[p] = chat[fft_freq(L, P, p)] / (double)L;
-  return out;
-}
 
 // Eigenvalues of tau(T_n) for k = 1..n (index k-1): t_0 + 2 sum_j t_j cos(j k pi/(n+1)).
 std::vector<double> tau_eigs(const std::vector<double>& t) {
@@ -266,21 +222,6 @@ std::vector<double> tau_eigs(const std::vector<double>& t) {
   return lam;
 }
 
-template <typename T>
-std::vector<T> twiddles(int L) {
-  std::vector<T> tw(2 * (size_t)L);
-  for (int j = 0; j < L; ++j) {
-    // exp(-2 pi i j / L) with exact symmetry in j
-    const int jj = j <= L / 2 ? j : L - j;
-    const double a = 2.0 * kPi * (double)jj / (double)L;
-    double c = std::cos(a), s = std::sin(a);
-    if (4 * jj == L) c = 0.0;
-    if (2 * jj == L) s = 0.0;
-    tw[2 * (size_t)j] = (T)c;
-    tw[2 * (size_t)j + 1] = (T)(j <= L / 2 ? -s : s);
-  }
-  return tw;
-}
 
 // In-place forward DFT X_f = sum_p a_p exp(-2 pi i p f / L), L a power of two
 // (iterative radix-2 with the symmetric twiddle table).
@@ -709,10 +650,11 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
     bnorm = vread(&hs->bnorm);
   }
   const double thresh = o->tol * bnorm;
-  // Reorthogonalisation: on request, and by default with the BF16
-  // preconditioner, whose rounding makes single-pass Gram-Schmidt lose
-  // orthogonality (the cycle minimum is then no longer the true residual).
-  const bool reorth = o->reorth > 0 || (o->reorth == 0 && tau && o->precision == RSFDE_BF16);
+  // Two Gram-Schmidt passes (CGS2) unless one is requested (reorth = -1):
+  // single-pass classical Gram-Schmidt loses orthogonality on long cycles at
+  // high stiffness (139 against 116 iterations per step at 2047^2, alpha = 1.9)
+  // and with the BF16 preconditioner's rounding.
+  const bool reorth = o->reorth >= 0;
   int total = 0, cycles = 0;
   double beta = 0.0;
   for (;;) {
