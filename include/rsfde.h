@@ -165,6 +165,29 @@ int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky);
  * Errors: EINVAL, EHIP. */
 int rsfde_matvec(rsfde_plan plan, const double* x, double* y, void* stream);
 
+/* y = M x as rsfde_matvec, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no plan, and no allocation of any kind.  The grid, orders,
+ * coefficients, mask (device, [n2][n1], 1 = in Omega), eta and dt are those of
+ * rsfde_setup; x, y are device [n2][n1] FP64 arrays owned by the caller and
+ * must not overlap.  Work is enqueued on `stream` (NULL: the null stream) on
+ * the current device.
+ * Scratch: one library-owned device array of 33 MiB per device (loaded with
+ * the code object, held until the process ends) holds the row-pass
+ * intermediate and the symbol and twiddle tables.  Limit: n1, n2 <= 2047.
+ * The symbol and twiddle tables are rebuilt on the device (one more kernel on
+ * `stream`, no host transfer) only when the grid, alpha1/alpha2 or the unit
+ * coefficients dt c_alpha / h^alpha change from the previous call on the
+ * device; otherwise the call enqueues the two kernels of the product.  The
+ * call never blocks the host.  Every call on a device shares that array:
+ * calls that overlap on one device (other streams, other host threads) race.
+ * Results equal rsfde_matvec's to rounding (the tables are the same sums,
+ * evaluated on the device).
+ * Errors: EINVAL (bad argument), EUNSUPPORTED (grid beyond the limit), EHIP. */
+int rsfde_matvec_noalloc(const rsfde_grid* grid, double alpha1, double alpha2, double kx,
+                         double ky, const uint8_t* mask_dev, double eta, double dt,
+                         const double* x, double* y, void* stream);
+
 /* z = P_hat^{-1} r (preconditioner): 2-D DST-I, the two eigenvalue scalings
  * 1/(1 - lx_i - ly_j) and 1/(1 + dt/eta - lx_i - ly_j), inverse 2-D DST-I,
  * combined by the mask.  precision selects the internal arithmetic: FP64 or

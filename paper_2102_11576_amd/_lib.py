@@ -84,6 +84,8 @@ def _load():
                                  C.c_double, C.c_int32, P]
     lib.rsfde_set_coeffs.argtypes = [P, C.c_double, C.c_double]
     lib.rsfde_matvec.argtypes = [P, P, P, P]
+    lib.rsfde_matvec_noalloc.argtypes = [C.POINTER(rsfde_grid), C.c_double, C.c_double, C.c_double,
+                                         C.c_double, P, C.c_double, C.c_double, P, P, P]
     lib.rsfde_precond_apply.argtypes = [P, P, P, C.c_int32, P]
     lib.rsfde_step.argtypes = [P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P,
                                C.POINTER(rsfde_stats), P]
@@ -102,7 +104,8 @@ def _load():
     lib.rsfde_destroy.argtypes = [P]
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
-    for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_matvec", "rsfde_precond_apply",
+    for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_matvec",
+              "rsfde_matvec_noalloc", "rsfde_precond_apply",
               "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_march_ensemble", "rsfde_adjoint_step", "rsfde_destroy",
               "rsfde_profile", "rsfde_profile_read"):
         getattr(lib, f).restype = C.c_int
@@ -206,6 +209,15 @@ def rsfde_set_coeffs(plan, kx, ky):
 
 def rsfde_matvec(plan, x, y, stream=None):
     _raise(_lib.rsfde_matvec(plan, _ptr(x), _ptr(y), _stream(stream)), "rsfde_matvec")
+
+
+def rsfde_matvec_noalloc(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, x, y, stream=None):
+    """y = M x without a plan and without any allocation (library-owned scratch
+    array; n1, n2 <= 2047)."""
+    g = rsfde_grid(int(n1), int(n2), float(box[0]), float(box[1]), float(box[2]), float(box[3]))
+    _raise(_lib.rsfde_matvec_noalloc(C.byref(g), float(alpha1), float(alpha2), float(kx), float(ky),
+                                     _ptr(mask), float(eta), float(dt), _ptr(x), _ptr(y),
+                                     _stream(stream)), "rsfde_matvec_noalloc")
 
 
 def rsfde_precond_apply(plan, r, z, precision=RSFDE_FP64, stream=None):

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "librsfde.so")
 
 SOURCES = ["kernels_mv.hip", "pc_f64.hip", "pc_f32.hip", "pc_chirp_f64.hip", "pc_chirp_f32.hip",
            "kernels_krylov.hip", "krylov_dot.hip", "krylov_axpy.hip", "krylov_update.hip",
-           "krylov_block.hip", "gemm_bf16.hip", "rsfde_host.cpp"]
+           "krylov_block.hip", "gemm_bf16.hip", "noalloc.hip", "rsfde_host.cpp"]
 ARCH = os.environ.get("RSFDE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -68,6 +68,18 @@ def test_host_validation_fails_fast(lib):
     assert lib.rsfde_setup(C.byref(h), C.byref(g), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 65, None) == -1
     big = rsfde_grid(8192, 15, 0.0, 1.0, 0.0, 1.0)
     assert lib.rsfde_setup(C.byref(h), C.byref(big), 1.5, 1.5, 1, 1, fake, 1e-6, .1, 20, None) == -7
+    # the allocation-free product validates on the host, before any device call
+    lib.rsfde_matvec_noalloc.argtypes = [C.POINTER(rsfde_grid), C.c_double, C.c_double, C.c_double,
+                                         C.c_double, P, C.c_double, C.c_double, P, P, P]
+    mv = lib.rsfde_matvec_noalloc
+    assert mv(None, 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -1
+    assert mv(C.byref(g), 1.5, 1.5, 1, 1, None, 1e-6, .1, fake, P(0x2000), None) == -1
+    assert mv(C.byref(g), 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, fake, None) == -1   # x == y
+    assert mv(C.byref(g), 2.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -1
+    assert mv(C.byref(g), 1.5, 1.5, 1, 1, fake, 0.0, .1, fake, P(0x2000), None) == -1
+    assert mv(C.byref(bad), 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -1
+    over = rsfde_grid(2048, 15, 0.0, 1.0, 0.0, 1.0)
+    assert mv(C.byref(over), 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -7
     # calls on a NULL plan
     lib.rsfde_matvec.argtypes = [P, P, P, P]
     assert lib.rsfde_matvec(None, fake, fake, None) == -1
