@@ -373,42 +373,69 @@ def configs_rates(log, sstep=10):
     return res
 
 
-def ensemble_rate(log, sstep=0, members=8, steps=8):
-    """Independent marches (FD directions / parameter sweeps) at 511^2 (c4 grid):
-    `members` plans advanced `steps` steps each, concurrently on their own
-    streams (rsfde_march_ensemble) against the same members one after another."""
+def ensemble_rate(log, sstep=0, steps=8):
+    """Independent marches of one grid (FD directions, parameter sweeps): B
+    members with their own kx and perturbed u0, advanced `steps` steps each,
+    three ways: one batched solve (rsfde_batch_step: every kernel launched once
+    for all members, one host decision per inner step for the batch), the
+    members as separate plans on their own streams (rsfde_march_ensemble), and
+    one member alone (the single-march rate).  The 511^2 differentiation grid
+    and the 63^2 grid of the small configuration, B = 8 and 16."""
+    import numpy as np
     import torch
-    from paper_2102_11576_amd import RsfdePlan, make_opts, march_ensemble
+    from paper_2102_11576_amd import RsfdeBatch, RsfdePlan, make_opts, march_ensemble
     from workloads.configs import make_config, fd_direction
-    w = make_config("c4")
     dev = torch.device("cuda:0")
-    opts = make_opts(w.restart, 100000, w.tol, sstep=sstep)
-    plans, u0s = [], []
-    for i in range(members):
-        plans.append(RsfdePlan.from_workload(w, kx=1.0 + 0.02 * i, device=dev))
-        du, _, _ = fd_direction(w.u0.shape, i)
-        u0s.append(torch.as_tensor(w.u0 + 1e-3 * du * w.mask, device=dev).reshape(-1).contiguous())
-    streams = [torch.cuda.Stream() for _ in plans]
-    march_ensemble(plans, u0s, 1, w.f_kind, opts, streams)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs, _ = march_ensemble(plans, u0s, steps, w.f_kind, opts, streams)
-    torch.cuda.synchronize()
-    t_conc = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for pl, u0 in zip(plans, u0s):
-        pl.march(u0, steps, w.f_kind, opts)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    for pl in plans:
-        pl.close()
-    unk = float(w.N) * steps * members
-    log(f"ensemble: {members} x {steps} steps at 511^2: {t_conc:.3f}s concurrent, {t_seq:.3f}s sequential")
-    return {"workload": f"{members} independent marches of {steps} steps on the 511x511 c4 grid "
-                        f"(perturbed u0, kx = 1 + 0.02 i)",
-            "concurrent_unknown_timesteps_per_s": unk / t_conc,
-            "sequential_unknown_timesteps_per_s": unk / t_seq,
-            "speedup": t_seq / t_conc}
+    out = {"note": "unknown*timesteps/s over all members; batched: one-vector FGMRES with two "
+                   "Gram-Schmidt passes; streams and single: the same form"}
+    for name in ("c4", "c1"):
+        w = make_config(name)
+        opts = make_opts(w.restart, 100000, w.tol, sstep=0)
+        single = None
+        for B in (8, 16):
+            kxs = [1.0 + 0.02 * i for i in range(B)]
+            kys = [w.ky] * B
+            u0s = []
+            for i in range(B):
+                du, _, _ = fd_direction(w.u0.shape, i)
+                u0s.append(w.u0 + 1e-3 * du * w.mask)
+            u0b = torch.as_tensor(np.stack(u0s), device=dev).reshape(-1).contiguous()
+            unk = float(w.N) * steps * B
+            with RsfdeBatch.from_workload(w, kxs, kys, device=dev) as bt:
+                bt.march(u0b, 1, w.f_kind, opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, itb = bt.march(u0b, steps, w.f_kind, opts)
+                torch.cuda.synchronize()
+                t_b = time.perf_counter() - t0
+            plans = [RsfdePlan.from_workload(w, kx=kxs[i], device=dev) for i in range(B)]
+            u0t = [torch.as_tensor(u, device=dev).reshape(-1).contiguous() for u in u0s]
+            streams = [torch.cuda.Stream() for _ in plans]
+            march_ensemble(plans, u0t, 1, w.f_kind, opts, streams)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            march_ensemble(plans, u0t, steps, w.f_kind, opts, streams)
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t0
+            if single is None:
+                plans[0].march(u0t[0], 1, w.f_kind, opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plans[0].march(u0t[0], steps, w.f_kind, opts)
+                torch.cuda.synchronize()
+                single = float(w.N) * steps / (time.perf_counter() - t0)
+            for pl in plans:
+                pl.close()
+            row = {"members": B, "steps": steps,
+                   "batched_unknown_timesteps_per_s": unk / t_b,
+                   "streams_unknown_timesteps_per_s": unk / t_s,
+                   "single_march_unknown_timesteps_per_s": single,
+                   "batched_over_streams": t_s / t_b,
+                   "batched_iters_per_member_step": float(np.mean(itb))}
+            out[f"{name}_{w.n1}_B{B}"] = row
+            log(f"ensemble {name} {w.n1}^2 B={B}: batched {row['batched_unknown_timesteps_per_s']:.3e}, "
+                f"streams {row['streams_unknown_timesteps_per_s']:.3e}, single {single:.3e}")
+    return out
 
 
 def three_d_rate(log, sstep=10, steps=4, profile=True, one_vector=True, fp32=True):
@@ -782,7 +809,7 @@ def main():
         out["adjoint"] = adjoint_rate(log, args.sstep)
 
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_rate(log, args.sstep)
+        out["ensemble"] = ensemble_rate(log)
 
     if not args.no_configs:
         out["configs"] = configs_rates(log, args.sstep)

@@ -243,6 +243,52 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
                        double* lam_prev, double* mu_guess, double* dk_dev, rsfde_stats* stats,
                        void* stream);
 
+/* Batched independent solves on one GPU (finite-difference directions,
+ * parameter sweeps, ensembles of initial fields).  The paper solves one
+ * system per time step; a batch runs `count` such steps (the step of
+ * rsfde_step for each member) in lockstep: every FFT pass and every streaming
+ * Krylov kernel is launched once for all members still iterating (the members
+ * are a grid dimension of each launch), and the host takes one convergence
+ * decision per inner step for the whole batch.  Members share the grid,
+ * alpha1, alpha2, the mask, eta and dt; each has its own kx, ky, vectors and
+ * Krylov state.  The solver is the one-vector flexible GMRES of rsfde_step
+ * (right preconditioning, two Gram-Schmidt passes unless opts->reorth = -1,
+ * stop when ||b - M x||_2 <= tol ||b||_2, FP64 or FP32 preconditioner).
+ *   count        : members, 1 .. 32 (EUNSUPPORTED above)
+ *   kx, ky       : host arrays of count coefficients, >= 0
+ *   other inputs : as rsfde_setup; n1 + 1 and n2 + 1 must be powers of two
+ *                  (EUNSUPPORTED otherwise)
+ * The batch owns one region of device memory per member (about
+ * (2 max_restart + 6) n1 n2 doubles plus the preconditioner intermediates)
+ * and count HostStatus records of pinned memory.
+ * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED. */
+typedef struct rsfde_batch_s* rsfde_batch;
+int rsfde_batch_setup(rsfde_batch* out, const rsfde_grid* grid, double alpha1, double alpha2,
+                      int32_t count, const double* kx, const double* ky,
+                      const uint8_t* mask_dev, double eta, double dt, int32_t max_restart,
+                      void* stream);
+/* New kx, ky for every member (host arrays of count).  Errors: EINVAL, EHIP. */
+int rsfde_batch_set_coeffs(rsfde_batch batch, const double* kx, const double* ky);
+/* y_m = M_m x_m for every member m: x, y are device arrays [count][n2][n1]
+ * (member after member) that must not overlap.  Errors: EINVAL, EHIP. */
+int rsfde_batch_matvec(rsfde_batch batch, const double* x, double* y, void* stream);
+/* z_m = P_hat_m^{-1} r_m for every member (FP64 or FP32 internals;
+ * EUNSUPPORTED for BF16).  Layout as rsfde_batch_matvec. */
+int rsfde_batch_precond_apply(rsfde_batch batch, const double* r, double* z, int32_t precision,
+                              void* stream);
+/* One implicit time step of every member (rsfde_step semantics per member):
+ * u_prev, u_prev2 (NULL at the first step), u_next are device arrays
+ * [count][n2][n1]; u_next must not alias u_prev.  stats: NULL or count
+ * entries, one per member.  opts: restart up to the batch's max_restart,
+ * precond RSFDE_PRECOND_TAU, side RSFDE_RIGHT, sstep 0 or 1 (EUNSUPPORTED
+ * otherwise).  Returns RSFDE_OK when every member converged, else the first
+ * member's failure code (each member's own code is in its stats entry; the
+ * other members' results are valid). */
+int rsfde_batch_step(rsfde_batch batch, const double* u_prev, const double* u_prev2,
+                     int32_t f_kind, const rsfde_solver_opts* opts, double* u_next,
+                     rsfde_stats* stats, void* stream);
+int rsfde_batch_destroy(rsfde_batch batch);
+
 /* Advance an ensemble of independent plans (finite-difference directions,
  * parameter sweeps, several initial fields: batched solves) by m
  * implicit steps each (rsfde_step semantics: initial guess 2u^{k-1} - u^{k-2},

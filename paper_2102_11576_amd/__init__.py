@@ -12,4 +12,4 @@ from ._lib import (  # noqa: F401
     rsfde_step, rsfde_solve, rsfde_adjoint_step, rsfde_destroy, strerror,
     RSFDE_F_NONE, RSFDE_F_LOGISTIC, RSFDE_F_SIN, RSFDE_F_CUBIC,
 )
-from .solver import RsfdePlan, StepStats, march_ensemble  # noqa: F401
+from .solver import RsfdePlan, RsfdeBatch, StepStats, march_ensemble  # noqa: F401

@@ -98,6 +98,15 @@ def _load():
     lib.rsfde_march_ensemble.argtypes = [C.c_int32, PP, PP, C.c_int32, C.c_int32,
                                          C.POINTER(rsfde_solver_opts), PP, PP,
                                          C.POINTER(rsfde_stats), PP]
+    DP = C.POINTER(C.c_double)
+    lib.rsfde_batch_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,
+                                      C.c_int32, DP, DP, P, C.c_double, C.c_double, C.c_int32, P]
+    lib.rsfde_batch_set_coeffs.argtypes = [P, DP, DP]
+    lib.rsfde_batch_matvec.argtypes = [P, P, P, P]
+    lib.rsfde_batch_precond_apply.argtypes = [P, P, P, C.c_int32, P]
+    lib.rsfde_batch_step.argtypes = [P, P, P, C.c_int32, C.POINTER(rsfde_solver_opts), P,
+                                     C.POINTER(rsfde_stats), P]
+    lib.rsfde_batch_destroy.argtypes = [P]
     lib.rsfde_profile.argtypes = [P, C.c_int32]
     lib.rsfde_profile_read.argtypes = [P, C.POINTER(rsfde_kernel_profile), C.c_int32,
                                        C.POINTER(C.c_int32)]
@@ -107,7 +116,9 @@ def _load():
     for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_matvec",
               "rsfde_matvec_noalloc", "rsfde_precond_apply",
               "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_march_ensemble", "rsfde_adjoint_step", "rsfde_destroy",
-              "rsfde_profile", "rsfde_profile_read"):
+              "rsfde_profile", "rsfde_profile_read", "rsfde_batch_setup", "rsfde_batch_set_coeffs",
+              "rsfde_batch_matvec", "rsfde_batch_precond_apply", "rsfde_batch_step",
+              "rsfde_batch_destroy"):
         getattr(lib, f).restype = C.c_int
     return lib
 
@@ -279,6 +290,54 @@ def rsfde_march_ensemble(plans, u0s, m, f_kind, opts, u_outs, works, streams=Non
     if check:
         _raise(rc, "rsfde_march_ensemble")
     return [st[i] for i in range(n)]
+
+
+def _dvec(vals):
+    vals = [float(v) for v in vals]
+    return (C.c_double * len(vals))(*vals)
+
+
+def rsfde_batch_setup(n1, n2, box, alpha1, alpha2, kxs, kys, mask, eta, dt, max_restart=30,
+                      stream=None):
+    import torch
+    if len(kxs) != len(kys):
+        raise ValueError("one kx and one ky per member")
+    _check_vec(mask, n1 * n2, "mask", torch.uint8)
+    g = rsfde_grid(int(n1), int(n2), float(box[0]), float(box[1]), float(box[2]), float(box[3]))
+    h = C.c_void_p()
+    rc = _lib.rsfde_batch_setup(C.byref(h), C.byref(g), float(alpha1), float(alpha2), len(kxs),
+                                _dvec(kxs), _dvec(kys), _ptr(mask), float(eta), float(dt),
+                                int(max_restart), _stream(stream))
+    _raise(rc, "rsfde_batch_setup")
+    return h
+
+
+def rsfde_batch_set_coeffs(batch, kxs, kys):
+    _raise(_lib.rsfde_batch_set_coeffs(batch, _dvec(kxs), _dvec(kys)), "rsfde_batch_set_coeffs")
+
+
+def rsfde_batch_matvec(batch, x, y, stream=None):
+    _raise(_lib.rsfde_batch_matvec(batch, _ptr(x), _ptr(y), _stream(stream)), "rsfde_batch_matvec")
+
+
+def rsfde_batch_precond_apply(batch, r, z, precision=RSFDE_FP64, stream=None):
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _raise(_lib.rsfde_batch_precond_apply(batch, _ptr(r), _ptr(z), p, _stream(stream)),
+           "rsfde_batch_precond_apply")
+
+
+def rsfde_batch_step(batch, count, u_prev, u_prev2, f_kind, opts, u_next, stream=None,
+                     check=True):
+    st = (rsfde_stats * count)()
+    rc = _lib.rsfde_batch_step(batch, _ptr(u_prev), _ptr(u_prev2), int(f_kind), C.byref(opts),
+                               _ptr(u_next), st, _stream(stream))
+    if check:
+        _raise(rc, "rsfde_batch_step")
+    return [st[i] for i in range(count)]
+
+
+def rsfde_batch_destroy(batch):
+    _raise(_lib.rsfde_batch_destroy(batch), "rsfde_batch_destroy")
 
 
 def rsfde_destroy(plan):

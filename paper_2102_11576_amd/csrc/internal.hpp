@@ -14,6 +14,24 @@ constexpr int kRedThreads = 256;      // threads per block of the streaming redu
 constexpr int kMaxRedBlocks = 512;    // upper bound on blocks of a streaming reduction
 constexpr int kMaxN = 4096;           // grid points per direction (FFT lengths <= 8192)
 
+// Members of a batched launch (independent solves of one grid, rsfde_batch_*):
+// slot k of the launch's member grid dimension works on member m[k], whose
+// per-member arrays start m[k] * stride doubles after the pointers the launch
+// is given.  A single plan launches one member with stride 0.
+constexpr int kMaxBatch = 32;
+struct Members {
+  int32_t n;             // members in the launch (grid dimension z of the FFT
+                         // kernels, y of the streaming Krylov kernels)
+  int32_t m[kMaxBatch];  // their member indices
+  size_t stride;         // doubles between consecutive members' arrays
+  __host__ __device__ size_t off(int k) const { return (size_t)m[k] * stride; }
+  static Members one() {
+    Members b{};
+    b.n = 1;
+    return b;
+  }
+};
+
 // Points per thread of the register-resident FFT of length L.
 constexpr int fft_pts(int L) { return L < 16 ? L : (L >= 8192 ? 8 : 16); }
 // Points per thread in pass B of the power-of-two preconditioner.
@@ -56,17 +74,21 @@ struct RedWork {
 // the symbol `sym` (already divided by L, stored in register-position order).
 // tiled: out in the strip-tiled layout (tile_index; 8 ceil(n1/4) ceil(n2/2)
 // values), as the column pass reads t on two-dimensional plans.
+// Batched (mb.n > 1 or a nonzero stride): z, out and sub advance by the
+// member offset; with mk given, coef = -mk[offset] (mk: the member's k).
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, double dpen, int mode, hipStream_t s,
-                          const double* sub = nullptr, double theta = 0.0, bool tiled = false);
+                          const double* sub = nullptr, double theta = 0.0, bool tiled = false,
+                          const Members& mb = Members::one(), const double* mk = nullptr);
 // Column pass: out = coef * (C_y z) + (mode==0 ? t : 0) on `batch` [n2][n1]
 // slices, slice b at offset b * bstride of z, t and out.  tiled (mode 0, one
 // slice): t in the strip-tiled layout.
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, int mode, hipStream_t s, int batch = 1,
-                          size_t bstride = 0, bool tiled = false);
+                          size_t bstride = 0, bool tiled = false,
+                          const Members& mb = Members::one(), const double* mk = nullptr);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
 // tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q is
@@ -74,16 +96,21 @@ hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
 // interleaved P1/P2 pairs (array P1, P2 unused) are in row segments
 // (pair_index; 2 W ceil((n1+1)/W) n2 T values, W = 64 / sizeof(T)).
 // Pass A: Q[r][slot] = raw x-sine sums of (sig * v) rows.
+// Batched: v, sig (when given), Q advance by the member offset (in doubles).
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q,
-                              const void* tw, int n1, int n2, bool tiled, hipStream_t s);
+                              const void* tw, int n1, int n2, bool tiled, hipStream_t s,
+                              const Members& mb = Members::one());
 // Pass B: column sine transforms of Q, the two eigenvalue scalings, two inverse
 // column transforms -> P1, P2 (slot layout in x, natural rows in y).
+// Batched: Q, P1, P2 advance by the member offset; with mk given, the
+// member's (kx, ky) are mk[offset], mk[offset + 1].
 template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2,
                           double kx, double ky, double dpen, double Kfac, bool tiled,
-                          hipStream_t s);
+                          hipStream_t s, const Members& mb = Members::one(),
+                          const double* mk = nullptr);
 // Raw sine transform (DST-I without normalisation) along the columns of
 // `batch` slices of [rows][ld] values (slice b at offset b * bstride):
 //   outA[k-1][ca] = sum_{p=1..rows} inA[p-1][ca] sin(pi k p / (rows + 1)), k = 1..rows,
@@ -98,18 +125,22 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw,
-                              int n1, int n2, bool tiled, hipStream_t s);
+                              int n1, int n2, bool tiled, hipStream_t s,
+                              const Members& mb = Members::one());
 
 // Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
 // t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL);
 // tiled: P1/P2 pairs in row segments, t strip-tiled over n1 columns.
+// Batched: P1, P2, z, t, sub advance by the member offset; with mk given,
+// coef = -mk[offset].
 template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
-                                 hipStream_t s);
+                                 hipStream_t s, const Members& mb = Members::one(),
+                                 const double* mk = nullptr);
 
 // Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
 // power of two): T internals, tables chn (n entries) and khat (L entries, in
@@ -140,27 +171,36 @@ hipError_t launch_pc_gemm_bf16(const double* v, const double* sig, double* z, co
 // ---------------------------- Krylov kernels ------------------------------
 // b = u + dt * mask * (f(u) + src_scale * src)  (src may be NULL), x0 = 2u - u2
 // (or u), ||b|| -> hs->bnorm.
+// Batched (Krylov kernels): every per-member pointer (vectors, bases, the
+// KrylovState, the reduction partials) advances by the member offset, and hs
+// is an array indexed by member; u and u2 advance by ustride per member.
 hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
                       int f_kind, const double* src, double src_scale, double* b, double* x0,
-                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s);
+                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s,
+                      const Members& mb = Members::one(), size_t ustride = 0);
 // ||v|| -> hs->bnorm.
 hipError_t launch_norm(const double* v, size_t N, RedWork rw, HostStatus* hs, hipStream_t s);
 hipError_t launch_residual(const double* b, const double* w, double* r, size_t N,
-                           RedWork rw, KrylovState* ks, HostStatus* hs, hipStream_t s);
+                           RedWork rw, KrylovState* ks, HostStatus* hs, hipStream_t s,
+                           const Members& mb = Members::one());
 // h_i = <v_i, w>, i < nv, into column j of H (second = false) or into ks->h2
 // (second = true: the reorthogonalisation pass).
 hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w, size_t N,
-                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s);
+                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s,
+                           const Members& mb = Members::one());
 // vout = w - sum_i c_i v_i with c = column j of H (second = false) or ks->h2;
 // finish = true also takes ||vout|| and does the Givens step (adding h2 into
 // column j first when second = true).
 hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w,
                               double* vout, size_t N, RedWork rw, KrylovState* ks, int j,
-                              bool second, bool finish, HostStatus* hs, hipStream_t s);
+                              bool second, bool finish, HostStatus* hs, hipStream_t s,
+                              const Members& mb = Members::one());
 // x += sum_{i<jc} y_i Z_i with R y = g; scaled = true multiplies y_i by
 // vscale[i] (Z = the unnormalised basis V: left preconditioning).
+// Batched: member slot k uses jc[k] vectors (jcs given; jc = their maximum).
 hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                         KrylovState* ks, bool scaled, hipStream_t s);
+                         KrylovState* ks, bool scaled, hipStream_t s,
+                         const Members& mb = Members::one(), const int32_t* jcs = nullptr);
 // x += sum_{i<jc} c_i Z_i with the coefficients c given (device array).
 // As launch_update with the coefficients y given on the host (jc doubles,
 // passed to the kernels as arguments).

@@ -55,8 +55,18 @@ __global__ __launch_bounds__(kRedThreads) void k_rhs(const double* __restrict__ 
                                                      const uint8_t* __restrict__ mask, double dt,
                                                      int f_kind, const double* __restrict__ src,
                                                      double src_scale, double* __restrict__ b,
-                                                     double* x0, size_t N, RedWork rw) {
+                                                     double* x0, size_t N, RedWork rw,
+                                                     const Members mb, size_t ustride) {
   __shared__ double sh[16 * 2];
+  {  // member of a batched launch (grid dimension y)
+    const size_t mo = mb.off(blockIdx.y), uo = (size_t)mb.m[blockIdx.y] * ustride;
+    u += uo;
+    if (u2) u2 += uo;
+    if (src) src += uo;
+    b += mo;
+    x0 += mo;
+    rw.partial += mo;
+  }
   double acc[2] = {0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -73,7 +83,10 @@ __global__ __launch_bounds__(kRedThreads) void k_rhs(const double* __restrict__ 
   publish_partials<2>(acc, 2, rw, sh);
 }
 
-__global__ __launch_bounds__(kFinishThreads) void k_rhs_finish(RedWork rw, int nb, HostStatus* hs) {
+__global__ __launch_bounds__(kFinishThreads) void k_rhs_finish(RedWork rw, int nb, HostStatus* hs,
+                                                               const Members mb) {
+  rw.partial += mb.off(blockIdx.y);
+  hs += mb.m[blockIdx.y];
   const int wv = threadIdx.x >> 6;
   if (wv > 0) return;
   const double bb = wave_total(rw, 0, nb);
@@ -89,8 +102,15 @@ __global__ __launch_bounds__(kFinishThreads) void k_rhs_finish(RedWork rw, int n
 __global__ __launch_bounds__(kRedThreads) void k_residual(const double* __restrict__ b,
                                                           const double* __restrict__ w,
                                                           double* __restrict__ r, size_t N,
-                                                          RedWork rw) {
+                                                          RedWork rw, const Members mb) {
   __shared__ double sh[16 * 1];
+  {
+    const size_t mo = mb.off(blockIdx.y);
+    b += mo;
+    w += mo;
+    r += mo;
+    rw.partial += mo;
+  }
   double acc[1] = {0.0};
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -104,8 +124,12 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(const double* __restri
 // Start of a restart cycle: beta = ||r||, g = (beta, 0, ...), vscale[0] = 1/beta.
 __global__ __launch_bounds__(kFinishThreads) void k_residual_finish(RedWork rw, int nb,
                                                                     KrylovState* ks,
-                                                                    HostStatus* hs) {
+                                                                    HostStatus* hs,
+                                                                    const Members mb) {
   if ((threadIdx.x >> 6) > 0) return;
+  rw.partial += mb.off(blockIdx.y);
+  ks = (KrylovState*)((double*)ks + mb.off(blockIdx.y));
+  hs += mb.m[blockIdx.y];
   const double rr = wave_total(rw, 0, nb);
   if (threadIdx.x == 0) {
     const double beta = sqrt(rr);
@@ -170,19 +194,23 @@ __global__ __launch_bounds__(kFinishThreads) void k_dot_finish(RedWork rw, int n
 
 hipError_t launch_rhs(const double* u, const double* u2, const uint8_t* mask, double dt,
                       int f_kind, const double* src, double src_scale, double* b, double* x0,
-                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s) {
+                      size_t N, RedWork rw, HostStatus* hs, hipStream_t s, const Members& mb,
+                      size_t ustride) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   const int nb = red_blocks(N);
-  hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(kRedThreads), 0, s, u, u2, mask, dt, f_kind, src,
-                     src_scale, b, x0, N, rw);
-  hipLaunchKernelGGL(k_rhs_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, hs);
+  hipLaunchKernelGGL(k_rhs, dim3(nb, mb.n), dim3(kRedThreads), 0, s, u, u2, mask, dt, f_kind, src,
+                     src_scale, b, x0, N, rw, mb, ustride);
+  hipLaunchKernelGGL(k_rhs_finish, dim3(1, mb.n), dim3(kFinishThreads), 0, s, rw, nb, hs, mb);
   return hipGetLastError();
 }
 
 hipError_t launch_residual(const double* b, const double* w, double* r, size_t N, RedWork rw,
-                           KrylovState* ks, HostStatus* hs, hipStream_t s) {
+                           KrylovState* ks, HostStatus* hs, hipStream_t s, const Members& mb) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   const int nb = red_blocks(N);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kRedThreads), 0, s, b, w, r, N, rw);
-  hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, ks, hs);
+  hipLaunchKernelGGL(k_residual, dim3(nb, mb.n), dim3(kRedThreads), 0, s, b, w, r, N, rw, mb);
+  hipLaunchKernelGGL(k_residual_finish, dim3(1, mb.n), dim3(kFinishThreads), 0, s, rw, nb, ks, hs,
+                     mb);
   return hipGetLastError();
 }
 

@@ -34,10 +34,18 @@ template <int L, bool TO>
 __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_rows(
     const double* __restrict__ z, const uint8_t* __restrict__ mask, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
-    double coef, double dpen, int mode, const double* __restrict__ sub, double theta) {
+    double coef, double dpen, int mode, const double* __restrict__ sub, double theta,
+    const Members mb, const double* __restrict__ mk) {
   using C = MvCfg<L>;
   using F = typename C::F;
   __shared__ double lds[C::BR * lds_len(L)];
+  {  // member of a batched launch (grid dimension z)
+    const size_t mo = mb.off(blockIdx.z);
+    z += mo;
+    out += mo;
+    if (sub) sub += mo;
+    if (mk) coef = -mk[mo];
+  }
   const int tid = threadIdx.x;
   const int b = tid / F::TPF, tau = tid % F::TPF;
   const int pair = blockIdx.x * C::BR + b;
@@ -98,12 +106,14 @@ template <int L, int MODE, bool TT>
 __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_cols(
     const double* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
-    double coef, size_t bstride) {
+    double coef, size_t bstride, const Members mb, const double* __restrict__ mk) {
   using C = MvCfg<L>;
   using F = typename C::F;
   __shared__ double lds[C::BC * lds_len(L)];
-  {
-    const size_t off = (size_t)blockIdx.y * bstride;
+  {  // slice (grid dimension y) and member of a batched launch (dimension z)
+    const size_t mo = mb.off(blockIdx.z);
+    if (mk) coef = -mk[mo];
+    const size_t off = (size_t)blockIdx.y * bstride + mo;
     z += off;
     out += off;
     if constexpr (MODE == 0) t += off;
@@ -159,39 +169,44 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
 template <int L>
 static hipError_t mv_rows_impl(const double* z, const uint8_t* mask, double* out, const double* sym,
                                const void* tw, int n1, int n2, double coef, double dpen, int mode,
-                               hipStream_t s, const double* sub, double theta, bool tiled) {
+                               hipStream_t s, const double* sub, double theta, bool tiled,
+                               const Members& mb, const double* mk) {
   using C = MvCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  const dim3 grid(blocks, 1, mb.n);
   if (tiled)
-    hipLaunchKernelGGL((k_mv_rows<L, true>), dim3(blocks), dim3(C::THR_R), 0, s, z, mask, out, sym,
-                       (const cpx<double>*)tw, n1, n2, coef, dpen, mode, sub, theta);
+    hipLaunchKernelGGL((k_mv_rows<L, true>), grid, dim3(C::THR_R), 0, s, z, mask, out, sym,
+                       (const cpx<double>*)tw, n1, n2, coef, dpen, mode, sub, theta, mb, mk);
   else
-    hipLaunchKernelGGL((k_mv_rows<L, false>), dim3(blocks), dim3(C::THR_R), 0, s, z, mask, out,
-                       sym, (const cpx<double>*)tw, n1, n2, coef, dpen, mode, sub, theta);
+    hipLaunchKernelGGL((k_mv_rows<L, false>), grid, dim3(C::THR_R), 0, s, z, mask, out,
+                       sym, (const cpx<double>*)tw, n1, n2, coef, dpen, mode, sub, theta, mb, mk);
   return hipGetLastError();
 }
 
 template <int L>
 static hipError_t mv_cols_impl(const double* z, const double* t, double* out, const double* sym,
                                const void* tw, int n1, int n2, double coef, int mode, hipStream_t s,
-                               int batch, size_t bstride, bool tiled) {
+                               int batch, size_t bstride, bool tiled, const Members& mb,
+                               const double* mk) {
   using C = MvCfg<L>;
   const int pairs = (n1 + 1) / 2;
   const int blocks = (pairs + C::BC - 1) / C::BC;
   if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
   if (tiled && (mode != 0 || batch != 1)) return hipErrorInvalidValue;
-  const dim3 grid(blocks, batch), thr(C::THR_C);
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  const dim3 grid(blocks, batch, mb.n), thr(C::THR_C);
   const cpx<double>* twc = (const cpx<double>*)tw;
   if (mode != 0)
     hipLaunchKernelGGL((k_mv_cols<L, 1, false>), grid, thr, 0, s, z, t, out, sym, twc, n1, n2,
-                       coef, bstride);
+                       coef, bstride, mb, mk);
   else if (tiled)
     hipLaunchKernelGGL((k_mv_cols<L, 0, true>), grid, thr, 0, s, z, t, out, sym, twc, n1, n2, coef,
-                       bstride);
+                       bstride, mb, mk);
   else
     hipLaunchKernelGGL((k_mv_cols<L, 0, false>), grid, thr, 0, s, z, t, out, sym, twc, n1, n2,
-                       coef, bstride);
+                       coef, bstride, mb, mk);
   return hipGetLastError();
 }
 
@@ -201,11 +216,12 @@ static hipError_t mv_cols_impl(const double* z, const double* t, double* out, co
 hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,
                           double dpen, int mode, hipStream_t s, const double* sub, double theta,
-                          bool tiled) {
+                          bool tiled, const Members& mb, const double* mk) {
   switch (L) {
-#define X(LL) \
-  case LL:    \
-    return mv_rows_impl<LL>(z, mask, out, sym, tw, n1, n2, coef, dpen, mode, s, sub, theta, tiled);
+#define X(LL)                                                                                    \
+  case LL:                                                                                       \
+    return mv_rows_impl<LL>(z, mask, out, sym, tw, n1, n2, coef, dpen, mode, s, sub, theta, tiled, \
+                            mb, mk);
     RSFDE_L_CASES(X)
 #undef X
     default:
@@ -215,11 +231,13 @@ hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* o
 
 hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,
-                          int mode, hipStream_t s, int batch, size_t bstride, bool tiled) {
+                          int mode, hipStream_t s, int batch, size_t bstride, bool tiled,
+                          const Members& mb, const double* mk) {
   switch (L) {
-#define X(LL) \
-  case LL:    \
-    return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s, batch, bstride, tiled);
+#define X(LL)                                                                                   \
+  case LL:                                                                                      \
+    return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s, batch, bstride, tiled, mb, \
+                            mk);
     RSFDE_L_CASES(X)
 #undef X
     default:

@@ -13,8 +13,18 @@ __global__ __launch_bounds__(kRedThreads) void k_axpy_givens(const double* __res
                                                              size_t ldv, const double* win,
                                                              double* vout, size_t N, RedWork rw,
                                                              const double* coef, int v0,
-                                                             const double* vscale) {
+                                                             const double* vscale,
+                                                             const Members mb) {
   __shared__ double sh[16 * 1];
+  {  // member of a batched launch (grid dimension y)
+    const size_t mo = mb.off(blockIdx.y);
+    V += mo;
+    win += mo;
+    vout += mo;
+    rw.partial += mo;
+    coef += mo;
+    vscale += mo;
+  }
   double c[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) c[v] = coef[v0 + v] * vscale[v0 + v];
@@ -49,8 +59,12 @@ __global__ __launch_bounds__(kRedThreads) void k_axpy_givens(const double* __res
 // beta = ||V_{j+1}||, H[j+1][j] = beta, vscale[j+1] = 1/beta, the previous
 // Givens rotations applied to column j, rotation j, and |g_{j+1}| for the host.
 __global__ __launch_bounds__(kFinishThreads) void k_givens(RedWork rw, int nb, KrylovState* ks,
-                                                           int j, int add_h2, HostStatus* hs) {
+                                                           int j, int add_h2, HostStatus* hs,
+                                                           const Members mb) {
   if ((threadIdx.x >> 6) > 0) return;
+  rw.partial += mb.off(blockIdx.y);
+  ks = (KrylovState*)((double*)ks + mb.off(blockIdx.y));
+  hs += mb.m[blockIdx.y];
   const double uu = wave_total(rw, 0, nb);
   if (threadIdx.x != 0) return;
   double* Hj = ks->H + (size_t)j * kLdH;
@@ -81,14 +95,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_givens(RedWork rw, int nb, K
 }
 
 using AxpyFn = void (*)(const double*, size_t, const double*, double*, size_t, RedWork,
-                        const double*, int, const double*, dim3, hipStream_t);
+                        const double*, int, const double*, const Members&, dim3, hipStream_t);
 
 template <int NV, bool FINAL>
 static void run_axpy(const double* V, size_t ldv, const double* win, double* vout, size_t N,
-                     RedWork rw, const double* coef, int v0, const double* vscale, dim3 g,
-                     hipStream_t s) {
+                     RedWork rw, const double* coef, int v0, const double* vscale,
+                     const Members& mb, dim3 g, hipStream_t s) {
   hipLaunchKernelGGL((k_axpy_givens<NV, FINAL>), g, dim3(kRedThreads), 0, s, V, ldv, win, vout, N,
-                     rw, coef, v0, vscale);
+                     rw, coef, v0, vscale, mb);
 }
 template <bool FINAL, int... I>
 static constexpr std::array<AxpyFn, sizeof...(I)> axpy_table(std::integer_sequence<int, I...>) {
@@ -99,8 +113,9 @@ static const auto kAxpyPart = axpy_table<false>(std::make_integer_sequence<int, 
 
 hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double* w, double* vout,
                               size_t N, RedWork rw, KrylovState* ks, int j, bool second,
-                              bool finish, HostStatus* hs, hipStream_t s) {
+                              bool finish, HostStatus* hs, hipStream_t s, const Members& mb) {
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   const double* coef = second ? ks->h2 : ks->H + (size_t)j * kLdH;
   for (int v0 = 0; v0 < nv; v0 += kChunk) {
     const int n = nv - v0 < kChunk ? nv - v0 : kChunk;
@@ -108,10 +123,10 @@ hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double*
     const double* win = v0 == 0 ? w : vout;
     const int nb = red_blocks(N);
     (last ? kAxpyFinal : kAxpyPart)[n - 1](V + (size_t)v0 * ldv, ldv, win, vout, N, rw, coef, v0,
-                                           ks->vscale, dim3(nb), s);
+                                           ks->vscale, mb, dim3(nb, mb.n), s);
     if (last)
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, ks, j,
-                         second ? 1 : 0, hs);
+      hipLaunchKernelGGL(k_givens, dim3(1, mb.n), dim3(kFinishThreads), 0, s, rw, nb, ks, j,
+                         second ? 1 : 0, hs, mb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -11,8 +11,14 @@ template <int NV>
 __global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restrict__ V, size_t ldv,
                                                           const double* __restrict__ w, size_t N,
                                                           RedWork rw, KrylovState* ks, int j,
-                                                          int v0) {
+                                                          int v0, const Members mb) {
   __shared__ double sh[16 * NV];
+  {  // member of a batched launch (grid dimension y)
+    const size_t mo = mb.off(blockIdx.y);
+    V += mo;
+    w += mo;
+    rw.partial += mo;
+  }
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
@@ -39,7 +45,13 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restri
 // dst is column j of H or the reorthogonalisation vector h2.
 __global__ __launch_bounds__(kFinishThreads) void k_multidot_finish(RedWork rw, int nb, int nv,
                                                                     KrylovState* ks, double* dst,
-                                                                    int v0) {
+                                                                    int v0, const Members mb) {
+  {
+    const size_t mo = mb.off(blockIdx.y);
+    rw.partial += mo;
+    ks = (KrylovState*)((double*)ks + mo);
+    dst += mo;
+  }
   const int lane = threadIdx.x & 63;
   for (int v = threadIdx.x >> 6; v < nv; v += kFinishThreads / 64) {
     const double t = wave_total(rw, v, nb);
@@ -48,12 +60,12 @@ __global__ __launch_bounds__(kFinishThreads) void k_multidot_finish(RedWork rw, 
 }
 
 using MultidotFn = void (*)(const double*, size_t, const double*, size_t, RedWork, KrylovState*,
-                            int, int, dim3, hipStream_t);
+                            int, int, const Members&, dim3, hipStream_t);
 
 template <int NV>
 static void run_multidot(const double* V, size_t ldv, const double* w, size_t N, RedWork rw,
-                         KrylovState* ks, int j, int v0, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot<NV>, g, dim3(kRedThreads), 0, s, V, ldv, w, N, rw, ks, j, v0);
+                         KrylovState* ks, int j, int v0, const Members& mb, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot<NV>, g, dim3(kRedThreads), 0, s, V, ldv, w, N, rw, ks, j, v0, mb);
 }
 template <int... I>
 static constexpr std::array<MultidotFn, sizeof...(I)> multidot_table(std::integer_sequence<int, I...>) {
@@ -62,15 +74,17 @@ static constexpr std::array<MultidotFn, sizeof...(I)> multidot_table(std::intege
 static const auto kMultidot = multidot_table(std::make_integer_sequence<int, kChunk>{});
 
 hipError_t launch_multidot(const double* V, size_t ldv, int nv, const double* w, size_t N,
-                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s) {
+                           RedWork rw, KrylovState* ks, int j, bool second, hipStream_t s,
+                           const Members& mb) {
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   double* dst = second ? ks->h2 : ks->H + (size_t)j * kLdH;
   for (int v0 = 0; v0 < nv; v0 += kChunk) {
     const int n = nv - v0 < kChunk ? nv - v0 : kChunk;
     const int nb = red_blocks(N);
-    kMultidot[n - 1](V + (size_t)v0 * ldv, ldv, w, N, rw, ks, j, v0, dim3(nb), s);
-    hipLaunchKernelGGL(k_multidot_finish, dim3(1), dim3(kFinishThreads), 0, s, rw, nb, n, ks, dst,
-                       v0);
+    kMultidot[n - 1](V + (size_t)v0 * ldv, ldv, w, N, rw, ks, j, v0, mb, dim3(nb, mb.n), s);
+    hipLaunchKernelGGL(k_multidot_finish, dim3(1, mb.n), dim3(kFinishThreads), 0, s, rw, nb, n, ks,
+                       dst, v0, mb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -68,10 +68,16 @@ struct PcColCfg {
 template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_fwd(
     const double* __restrict__ v, const double* __restrict__ sig, T* __restrict__ Q,
-    const cpx<T>* __restrict__ tw, int n1, int n2) {
+    const cpx<T>* __restrict__ tw, int n1, int n2, const Members mb) {
   using C = PcCfg<L>;
   using F = typename C::F;
   __shared__ T lds[C::BR * lds_len(L)];
+  {  // member of a batched launch (grid dimension z); offsets in doubles
+    const size_t mo = mb.off(blockIdx.z);
+    v += mo;
+    if (sig) sig += mo;
+    Q += mo * (sizeof(double) / sizeof(T));
+  }
   const int tid = threadIdx.x;
   const int b = tid / F::TPF, tau = tid % F::TPF;
   const int pair = blockIdx.x * C::BR + b;
@@ -156,10 +162,22 @@ template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
     const T* __restrict__ Q, T* __restrict__ P1, T* __restrict__ P2,
     const T* __restrict__ lamx_slot, const T* __restrict__ lamy_pos,
-    const cpx<T>* __restrict__ tw, int n1, int n2, T kx, T ky, T dpen, T halfK) {
+    const cpx<T>* __restrict__ tw, int n1, int n2, T kx, T ky, T dpen, T halfK, const Members mb,
+    const double* __restrict__ mk) {
   using C = PcColCfg<L>;
   using F = typename C::F;
   __shared__ T lds[C::BC * lds_len(L)];
+  {  // member of a batched launch (grid dimension z)
+    const size_t mo = mb.off(blockIdx.z);
+    const size_t mt = mo * (sizeof(double) / sizeof(T));
+    Q += mt;
+    P1 += mt;
+    if (P2) P2 += mt;
+    if (mk) {
+      kx = (T)mk[mo];
+      ky = (T)mk[mo + 1];
+    }
+  }
   const int tid = threadIdx.x;
   const int b = tid % C::BC, tau = tid / C::BC;
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
@@ -374,10 +392,16 @@ template <typename T, int L, bool TL>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
     const T* __restrict__ P1, const T* __restrict__ P2,
     const uint8_t* __restrict__ mask, double* __restrict__ z, const cpx<T>* __restrict__ tw,
-    int n1, int n2) {
+    int n1, int n2, const Members mb) {
   using C = PcCfg<L>;
   using F = typename C::F;
   __shared__ T lds[C::BR * lds_len(L)];
+  {  // member of a batched launch (grid dimension z)
+    const size_t mo = mb.off(blockIdx.z);
+    P1 += mo * (sizeof(double) / sizeof(T));
+    if (P2) P2 += mo * (sizeof(double) / sizeof(T));
+    z += mo;
+  }
   const int tid = threadIdx.x;
   const int b = tid / F::TPF, tau = tid % F::TPF;
   const int r = blockIdx.x * C::BR + b;
@@ -420,10 +444,20 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
                       double* __restrict__ z, double* __restrict__ t,
                       const cpx<T>* __restrict__ twT, const cpx<double>* __restrict__ tw64,
                       const double* __restrict__ sym, double coef, double dpen,
-                      const double* __restrict__ sub, double theta, int n1, int n2) {
+                      const double* __restrict__ sub, double theta, int n1, int n2,
+                      const Members mb, const double* __restrict__ mk) {
   using C = PcCfg<L>;
   using F = typename C::F;
   __shared__ double lds[C::BR * lds_len(L)];
+  {  // member of a batched launch (grid dimension z)
+    const size_t mo = mb.off(blockIdx.z);
+    P1 += mo * (sizeof(double) / sizeof(T));
+    if (P2) P2 += mo * (sizeof(double) / sizeof(T));
+    z += mo;
+    t += mo;
+    if (sub) sub += mo;
+    if (mk) coef = -mk[mo];
+  }
   const int tid = threadIdx.x;
   const int b = tid / F::TPF, tau = tid % F::TPF;
   const int pair = blockIdx.x * C::BR + b;
@@ -508,35 +542,39 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
 // ------------------------------- launchers --------------------------------
 template <typename T, int L, bool TL>
 static hipError_t pc_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* tw,
-                                   int n1, int n2, hipStream_t s) {
+                                   int n1, int n2, hipStream_t s, const Members& mb) {
   using C = PcCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_fwd<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, v, sig, Q,
-                     (const cpx<T>*)tw, n1, n2);
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pc_rows_fwd<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_R), 0, s, v,
+                     sig, Q, (const cpx<T>*)tw, n1, n2, mb);
   return hipGetLastError();
 }
 
 template <typename T, int L, bool TL>
 static hipError_t pc_cols_impl(const T* Q, T* P1, T* P2, const T* lamx, const T* lamy,
                                const void* tw, int n1, int n2, double kx, double ky, double dpen,
-                               double Kfac, hipStream_t s) {
+                               double Kfac, hipStream_t s, const Members& mb, const double* mk) {
   using C = PcColCfg<L>;
   const int pairs = (n1 + 1) / 2;
   const int blocks = (pairs + C::BC - 1) / C::BC;
-  hipLaunchKernelGGL((k_pc_cols<T, L, TL>), dim3(blocks), dim3(C::THR_C), 0, s, Q, P1, P2, lamx, lamy,
-                     (const cpx<T>*)tw, n1, n2, (T)kx, (T)ky, (T)dpen, (T)(0.5 * Kfac));
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pc_cols<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_C), 0, s, Q, P1, P2,
+                     lamx, lamy, (const cpx<T>*)tw, n1, n2, (T)kx, (T)ky, (T)dpen,
+                     (T)(0.5 * Kfac), mb, mk);
   return hipGetLastError();
 }
 
 template <typename T, int L, bool TL>
 static hipError_t pc_rows_inv_impl(const T* P1, const T* P2,
                                    const uint8_t* mask, double* z, const void* tw, int n1, int n2,
-                                   hipStream_t s) {
+                                   hipStream_t s, const Members& mb) {
   using C = PcCfg<L>;
   const int blocks = (n2 + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
-                     mask, z, (const cpx<T>*)tw, n1, n2);
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pc_rows_inv<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_R), 0, s, P1,
+                     P2, mask, z, (const cpx<T>*)tw, n1, n2, mb);
   return hipGetLastError();
 }
 
@@ -545,13 +583,14 @@ static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
                                       const uint8_t* mask, double* z, double* t, const void* twT,
                                       const void* tw64, const double* sym, double coef,
                                       double dpen, const double* sub, double theta, int n1,
-                                      int n2, hipStream_t s) {
+                                      int n2, hipStream_t s, const Members& mb, const double* mk) {
   using C = PcCfg<L>;
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
-  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL>), dim3(blocks), dim3(C::THR_R), 0, s, P1, P2,
-                     mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
-                     sub, theta, n1, n2);
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_R), 0, s, P1,
+                     P2, mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
+                     sub, theta, n1, n2, mb, mk);
   return hipGetLastError();
 }
 
@@ -572,12 +611,12 @@ static hipError_t dst_cols_impl(const T* inA, const T* inB, T* outA, T* outB, co
 
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, const void* tw,
-                              int n1, int n2, bool tiled, hipStream_t s) {
+                              int n1, int n2, bool tiled, hipStream_t s, const Members& mb) {
   switch (Lx) {
-#define X(LL)                                                           \
-  case LL:                                                              \
-    return tiled ? pc_rows_fwd_impl<T, LL, true>(v, sig, Q, tw, n1, n2, s) \
-                 : pc_rows_fwd_impl<T, LL, false>(v, sig, Q, tw, n1, n2, s);
+#define X(LL)                                                               \
+  case LL:                                                                  \
+    return tiled ? pc_rows_fwd_impl<T, LL, true>(v, sig, Q, tw, n1, n2, s, mb) \
+                 : pc_rows_fwd_impl<T, LL, false>(v, sig, Q, tw, n1, n2, s, mb);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -588,14 +627,15 @@ hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, 
 template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2, double kx, double ky,
-                          double dpen, double Kfac, bool tiled, hipStream_t s) {
+                          double dpen, double Kfac, bool tiled, hipStream_t s, const Members& mb,
+                          const double* mk) {
   switch (Ly) {
 #define X(LL)                                                                                   \
   case LL:                                                                                      \
     return tiled ? pc_cols_impl<T, LL, true>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, \
-                                             dpen, Kfac, s)                                     \
+                                             dpen, Kfac, s, mb, mk)                             \
                  : pc_cols_impl<T, LL, false>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx,   \
-                                              ky, dpen, Kfac, s);
+                                              ky, dpen, Kfac, s, mb, mk);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -622,12 +662,12 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw, int n1, int n2,
-                              bool tiled, hipStream_t s) {
+                              bool tiled, hipStream_t s, const Members& mb) {
   switch (Lx) {
-#define X(LL)                                                                  \
-  case LL:                                                                     \
-    return tiled ? pc_rows_inv_impl<T, LL, true>(P1, P2, mask, z, tw, n1, n2, s) \
-                 : pc_rows_inv_impl<T, LL, false>(P1, P2, mask, z, tw, n1, n2, s);
+#define X(LL)                                                                      \
+  case LL:                                                                         \
+    return tiled ? pc_rows_inv_impl<T, LL, true>(P1, P2, mask, z, tw, n1, n2, s, mb) \
+                 : pc_rows_inv_impl<T, LL, false>(P1, P2, mask, z, tw, n1, n2, s, mb);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -640,14 +680,14 @@ hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, double* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
-                                 hipStream_t s) {
+                                 hipStream_t s, const Members& mb, const double* mk) {
   switch (L) {
 #define X(LL)                                                                                    \
   case LL:                                                                                       \
     return tiled ? pc_rows_inv_mv_impl<T, LL, true>(P1, P2, mask, z, t, twT, tw64, sym, coef,    \
-                                                    dpen, sub, theta, n1, n2, s)                 \
+                                                    dpen, sub, theta, n1, n2, s, mb, mk)         \
                  : pc_rows_inv_mv_impl<T, LL, false>(P1, P2, mask, z, t, twT, tw64, sym, coef,   \
-                                                     dpen, sub, theta, n1, n2, s);
+                                                     dpen, sub, theta, n1, n2, s, mb, mk);
     RSFDE_LD_CASES(X)
 #undef X
     default:

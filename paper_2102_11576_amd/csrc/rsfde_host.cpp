@@ -1707,3 +1707,391 @@ int rsfde_destroy(rsfde_plan plan) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched independent solves (rsfde_batch_*): B members share the grid, the
+// orders, the mask, eta and dt, and each has its own kx, ky, right-hand side
+// and Krylov state.  Every operator and Krylov kernel runs once per step for
+// all members still iterating (the members are a grid dimension of each
+// launch), and the host takes one decision per inner step for the whole
+// batch.  Each member owns one region of the batch allocation, the same
+// layout at a fixed stride: KrylovState, reduction partials, its (kx, ky),
+// the bases V and Z, b, w, t, x and the preconditioner intermediates.
+// ---------------------------------------------------------------------------
+
+struct rsfde_batch_s {
+  rsfde_plan plan = nullptr;  // tables (symbols, eigenvalues, twiddles) and the mask
+  int B = 0;
+  size_t MS = 0;              // member stride (doubles)
+  double* region = nullptr;   // B * MS doubles
+  size_t o_ks = 0, o_part = 0, o_k = 0, o_V = 0, o_Z = 0, o_b = 0, o_w = 0, o_t = 0, o_x = 0,
+         o_Q = 0, o_P1 = 0;
+  rsfde::HostStatus* hs = nullptr;      // pinned [B]
+  rsfde::HostStatus* hs_dev = nullptr;
+  hipEvent_t ev = nullptr;
+  std::vector<double> kx, ky;
+  ~rsfde_batch_s() {
+    if (region) (void)hipFree(region);
+    if (hs) (void)hipHostFree(hs);
+    if (ev) (void)hipEventDestroy(ev);
+    if (plan) rsfde_destroy(plan);
+  }
+};
+
+namespace rsfde {
+namespace {
+
+size_t r64(size_t v) { return (v + 63) / 64 * 64; }
+
+Members members_of(const rsfde_batch_s* Bt, const std::vector<int>& ids) {
+  Members mb{};
+  mb.n = (int)ids.size();
+  for (int k = 0; k < mb.n; ++k) mb.m[k] = ids[k];
+  mb.stride = Bt->MS;
+  return mb;
+}
+
+// w = M x for the members of mb (vectors at member-0 addresses of the region).
+int batch_matvec(rsfde_batch_s* Bt, const double* x, double* w, const Members& mb, hipStream_t s) {
+  Plan* P = &Bt->plan->p;
+  const double* mk = Bt->region + Bt->o_k;
+  double* t = Bt->region + Bt->o_t;
+  CK(launch_mv_rows(P->Lcx, x, P->mask, t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, 0.0, P->dpen, 0,
+                    s, nullptr, 0.0, true, mb, mk));
+  CK(launch_mv_cols(P->Lcy, x, t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, 0.0, 0, s, 1, 0, true,
+                    mb, mk + 1));
+  return RSFDE_OK;
+}
+
+// The three preconditioner passes (power-of-two path) for the members of mb:
+// Q, P1 from the region; with w given, the last pass is fused with the
+// matrix-vector row pass and the column pass completes w = M z.
+template <typename T>
+int batch_precond(rsfde_batch_s* Bt, const double* v, const double* sig, double* z, double* w,
+                  const Members& mb, hipStream_t s) {
+  Plan* P = &Bt->plan->p;
+  const double* mk = Bt->region + Bt->o_k;
+  T* Q = (T*)(Bt->region + Bt->o_Q);
+  T* P1 = (T*)(Bt->region + Bt->o_P1);
+  auto& tw = sizeof(T) == 8 ? P->tw64 : P->tw32;
+  const T* lamx = sizeof(T) == 8 ? (const T*)P->lamx64 : (const T*)P->lamx32;
+  const T* lamy = sizeof(T) == 8 ? (const T*)P->lamy64 : (const T*)P->lamy32;
+  const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
+  CK(launch_pc_rows_fwd<T>(P->Ldx, v, sig, Q, tw[P->Ldx], P->n1, P->n2, true, s, mb));
+  CK(launch_pc_cols<T>(P->Ldy, Q, P1, nullptr, lamx, lamy, tw[P->Ldy], P->n1, P->n2, 0.0, 0.0,
+                       P->dpen, Kfac, true, s, mb, mk));
+  if (!w) {
+    CK(launch_pc_rows_inv<T>(P->Ldx, P1, nullptr, P->mask, z, tw[P->Ldx], P->n1, P->n2, true, s,
+                             mb));
+    return RSFDE_OK;
+  }
+  double* t = Bt->region + Bt->o_t;
+  CK(launch_pc_rows_inv_mv<T>(P->Ldx, P1, nullptr, P->mask, z, t, tw[P->Ldx], P->tw64[P->Ldx],
+                              P->symx, 0.0, P->dpen, nullptr, 0.0, P->n1, P->n2, true, s, mb, mk));
+  CK(launch_mv_cols(P->Lcy, z, t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, 0.0, 0, s, 1, 0, true,
+                    mb, mk + 1));
+  return RSFDE_OK;
+}
+
+int batch_precond_any(rsfde_batch_s* Bt, int precision, const double* v, const double* sig,
+                      double* z, double* w, const Members& mb, hipStream_t s) {
+  return precision == RSFDE_FP32 ? batch_precond<float>(Bt, v, sig, z, w, mb, s)
+                                 : batch_precond<double>(Bt, v, sig, z, w, mb, s);
+}
+
+// Flexible GMRES(restart), one Arnoldi vector per step (two Gram-Schmidt
+// passes unless reorth = -1), right preconditioning, for every member at once:
+// the same algorithm and stopping rule as the single-plan one-vector form
+// (true residual ||b - M x|| <= tol ||b|| at the start of every cycle, the
+// residual estimate ending a cycle early).  b and x0 are in the region;
+// hs[m].bnorm holds ||b_m||.
+int batch_solve(rsfde_batch_s* Bt, const rsfde_solver_opts* o, rsfde_stats* st, hipStream_t s) {
+  Plan* P = &Bt->plan->p;
+  const int B = Bt->B;
+  const size_t N = P->N, ld = P->ldv;
+  volatile HostStatus* hs = Bt->hs;
+  const bool reorth = o->reorth >= 0;
+  double* R = Bt->region;
+  KrylovState* ks = (KrylovState*)(R + Bt->o_ks);
+  RedWork rw{R + Bt->o_part};
+  double *V = R + Bt->o_V, *Zb = R + Bt->o_Z, *b = R + Bt->o_b, *w = R + Bt->o_w, *x = R + Bt->o_x;
+  CK(hipStreamSynchronize(s));
+  std::vector<int> total(B, 0), cycles(B, 0), status(B, RSFDE_OK);
+  std::vector<double> bnorm(B), thresh(B), beta(B, 0.0);
+  std::vector<int> active;
+  for (int m = 0; m < B; ++m) {
+    bnorm[m] = hs[m].bnorm;
+    thresh[m] = o->tol * bnorm[m];
+    if (hs[m].flags & kFlagNonFinite) {
+      status[m] = RSFDE_ENONFINITE;
+    } else if (bnorm[m] == 0.0) {
+      CK(hipMemsetAsync(x + (size_t)m * Bt->MS, 0, N * sizeof(double), s));
+    } else {
+      active.push_back(m);
+    }
+  }
+  while (!active.empty()) {
+    const Members ma = members_of(Bt, active);
+    if (int rc = batch_matvec(Bt, x, w, ma, s)) return rc;
+    CK(launch_residual(b, w, V, N, rw, ks, Bt->hs_dev, s, ma));
+    CK(hipStreamSynchronize(s));
+    std::vector<int> iterating;
+    for (int m : active) {
+      beta[m] = hs[m].beta;
+      if (hs[m].flags & kFlagNonFinite) status[m] = RSFDE_ENONFINITE;
+      else if (beta[m] <= thresh[m]) status[m] = RSFDE_OK;
+      else if (total[m] >= o->max_iters) status[m] = RSFDE_ENOTCONV;
+      else {
+        iterating.push_back(m);
+        ++cycles[m];
+      }
+    }
+    active = iterating;
+    if (active.empty()) break;
+    std::vector<int> jc(B, 0);
+    for (int j = 0; j < o->restart && !iterating.empty(); ++j) {
+      const Members mi = members_of(Bt, iterating);
+      double* vj = V + (size_t)j * ld;
+      double* zj = Zb + (size_t)j * ld;
+      double* vnext = V + (size_t)(j + 1) * ld;
+      if (int rc = batch_precond_any(Bt, o->precision, vj, &ks->vscale[j], zj, w, mi, s)) return rc;
+      CK(launch_multidot(V, ld, j + 1, w, N, rw, ks, j, false, s, mi));
+      CK(launch_axpy_givens(V, ld, j + 1, w, vnext, N, rw, ks, j, false, !reorth, Bt->hs_dev, s, mi));
+      if (reorth) {
+        CK(launch_multidot(V, ld, j + 1, vnext, N, rw, ks, j, true, s, mi));
+        CK(launch_axpy_givens(V, ld, j + 1, vnext, vnext, N, rw, ks, j, true, true, Bt->hs_dev, s,
+                              mi));
+      }
+      CK(hipEventRecord(Bt->ev, s));
+      CK(hipEventSynchronize(Bt->ev));
+      std::vector<int> still;
+      for (int m : iterating) {
+        ++total[m];
+        const bool bad = (hs[m].flags & kFlagNonFinite) != 0;
+        if (bad || hs[m].est[j] <= thresh[m] || j + 1 == o->restart || total[m] >= o->max_iters)
+          jc[m] = j + 1;
+        else
+          still.push_back(m);
+      }
+      iterating = still;
+    }
+    std::vector<int32_t> jcs;
+    int jmax = 0;
+    for (int m : active) {
+      jcs.push_back(jc[m]);
+      jmax = std::max(jmax, jc[m]);
+    }
+    CK(launch_update(Zb, ld, jmax, x, N, ks, false, s, members_of(Bt, active), jcs.data()));
+  }
+  CK(hipStreamSynchronize(s));
+  int rc_all = RSFDE_OK;
+  for (int m = 0; m < B; ++m) {
+    finish(st ? &st[m] : nullptr, status[m], total[m], cycles[m], beta[m], bnorm[m]);
+    if (status[m] != RSFDE_OK && rc_all == RSFDE_OK) rc_all = status[m];
+  }
+  return rc_all;
+}
+
+// Copy B vectors between a caller array [B][N] and region slot `off`.
+hipError_t batch_copy(rsfde_batch_s* Bt, double* dst, size_t dpitch, const double* src,
+                      size_t spitch, hipStream_t s) {
+  const size_t N = Bt->plan->p.N;
+  return hipMemcpy2DAsync(dst, dpitch * sizeof(double), src, spitch * sizeof(double),
+                          N * sizeof(double), (size_t)Bt->B, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace
+}  // namespace rsfde
+
+extern "C" {
+
+int rsfde_batch_setup(rsfde_batch* out, const rsfde_grid* grid, double alpha1, double alpha2,
+                      int32_t count, const double* kx, const double* ky, const uint8_t* mask_dev,
+                      double eta, double dt, int32_t max_restart, void* stream) {
+  using namespace rsfde;
+  if (!out) return RSFDE_EINVAL;
+  *out = nullptr;
+  if (!grid || !kx || !ky || !mask_dev || count < 1) return RSFDE_EINVAL;
+  if (count > kMaxBatch) return RSFDE_EUNSUPPORTED;
+  for (int m = 0; m < count; ++m)
+    if (!(kx[m] >= 0.0) || !(ky[m] >= 0.0) || !std::isfinite(kx[m]) || !std::isfinite(ky[m]))
+      return RSFDE_EINVAL;
+  if (max_restart <= 0) max_restart = 30;
+  if (max_restart > kMaxRestart) return RSFDE_EINVAL;
+  if (grid->n1 >= 1 && grid->n2 >= 1 && (!is_pow2(grid->n1 + 1) || !is_pow2(grid->n2 + 1)))
+    return RSFDE_EUNSUPPORTED;  // the batched passes are the power-of-two (odd-extension) ones
+  auto* Bt = new (std::nothrow) rsfde_batch_s();
+  if (!Bt) return RSFDE_ENOMEM;
+  int rc = rsfde_setup(&Bt->plan, grid, alpha1, alpha2, kx[0], ky[0], mask_dev, eta, dt, 1, stream);
+  if (rc) {
+    delete Bt;
+    return rc;
+  }
+  Plan* P = &Bt->plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard g(P->dev);
+  if (!g.ok) {
+    delete Bt;
+    return RSFDE_EHIP;
+  }
+  Bt->B = count;
+  Bt->kx.assign(kx, kx + count);
+  Bt->ky.assign(ky, ky + count);
+  const size_t ld = P->ldv, n1 = P->n1, n2 = P->n2;
+  const size_t slots = 8 * ((n1 + 4) / 4) * ((n2 + 1) / 2);
+  const size_t pair_slots = 2 * ((n1 + 16) / 16 * 16) * n2;
+  const size_t t_len = std::max(ld, 8 * ((n1 + 3) / 4) * ((n2 + 1) / 2));
+  size_t o = 0;
+  auto take = [&](size_t& off, size_t count_d) {
+    off = o;
+    o += r64(count_d);
+  };
+  take(Bt->o_ks, (sizeof(KrylovState) + 7) / 8);
+  take(Bt->o_part, (size_t)(kMaxRestart + 2) * kMaxRedBlocks);
+  take(Bt->o_k, 2);
+  take(Bt->o_V, (size_t)(max_restart + 1) * ld);
+  take(Bt->o_Z, (size_t)max_restart * ld);
+  take(Bt->o_b, ld);
+  take(Bt->o_w, ld);
+  take(Bt->o_t, t_len);
+  take(Bt->o_x, ld);
+  take(Bt->o_Q, slots);
+  take(Bt->o_P1, std::max(2 * slots, pair_slots));
+  Bt->MS = o;
+  if (hipMalloc((void**)&Bt->region, (size_t)count * Bt->MS * sizeof(double)) != hipSuccess) {
+    Bt->region = nullptr;
+    delete Bt;
+    return RSFDE_ENOMEM;
+  }
+  if (hipHostMalloc((void**)&Bt->hs, (size_t)count * sizeof(HostStatus),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    Bt->hs = nullptr;
+    delete Bt;
+    return RSFDE_ENOMEM;
+  }
+  std::memset((void*)Bt->hs, 0, (size_t)count * sizeof(HostStatus));
+  if (hipHostGetDevicePointer((void**)&Bt->hs_dev, Bt->hs, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&Bt->ev, hipEventDisableTiming) != hipSuccess) {
+    delete Bt;
+    return RSFDE_EHIP;
+  }
+  for (int m = 0; m < count; ++m) {
+    double* base = Bt->region + (size_t)m * Bt->MS;
+    const double k2[2] = {kx[m], ky[m]};
+    if (hipMemsetAsync(base + Bt->o_ks, 0, sizeof(KrylovState), s) != hipSuccess ||
+        hipMemcpyAsync(base + Bt->o_k, k2, sizeof(k2), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      delete Bt;
+      return RSFDE_EHIP;
+    }
+  }
+  *out = Bt;
+  return RSFDE_OK;
+}
+
+int rsfde_batch_set_coeffs(rsfde_batch batch, const double* kx, const double* ky) {
+  if (!batch || !kx || !ky) return RSFDE_EINVAL;
+  for (int m = 0; m < batch->B; ++m)
+    if (!(kx[m] >= 0.0) || !(ky[m] >= 0.0) || !std::isfinite(kx[m]) || !std::isfinite(ky[m]))
+      return RSFDE_EINVAL;
+  rsfde::DeviceGuard g(batch->plan->p.dev);
+  if (!g.ok) return RSFDE_EHIP;
+  for (int m = 0; m < batch->B; ++m) {
+    const double k2[2] = {kx[m], ky[m]};
+    if (hipMemcpy(batch->region + (size_t)m * batch->MS + batch->o_k, k2, sizeof(k2),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return RSFDE_EHIP;
+    batch->kx[m] = kx[m];
+    batch->ky[m] = ky[m];
+  }
+  return RSFDE_OK;
+}
+
+int rsfde_batch_matvec(rsfde_batch batch, const double* x, double* y, void* stream) {
+  using namespace rsfde;
+  if (!batch || !x || !y || x == y) return RSFDE_EINVAL;
+  Plan* P = &batch->plan->p;
+  DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  hipStream_t s = pick(P, stream);
+  std::vector<int> all(batch->B);
+  for (int m = 0; m < batch->B; ++m) all[m] = m;
+  double* xr = batch->region + batch->o_x;
+  double* wr = batch->region + batch->o_w;
+  CK(batch_copy(batch, xr, batch->MS, x, P->N, s));
+  if (int rc = batch_matvec(batch, xr, wr, members_of(batch, all), s)) return rc;
+  CK(batch_copy(batch, y, P->N, wr, batch->MS, s));
+  return RSFDE_OK;
+}
+
+int rsfde_batch_precond_apply(rsfde_batch batch, const double* r, double* z, int32_t precision,
+                              void* stream) {
+  using namespace rsfde;
+  if (!batch || !r || !z || r == z) return RSFDE_EINVAL;
+  if (precision != RSFDE_FP64 && precision != RSFDE_FP32) return RSFDE_EUNSUPPORTED;
+  Plan* P = &batch->plan->p;
+  DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  hipStream_t s = pick(P, stream);
+  std::vector<int> all(batch->B);
+  for (int m = 0; m < batch->B; ++m) all[m] = m;
+  double* xr = batch->region + batch->o_x;
+  double* wr = batch->region + batch->o_w;
+  CK(batch_copy(batch, xr, batch->MS, r, P->N, s));
+  if (int rc = batch_precond_any(batch, precision, xr, nullptr, wr, nullptr, members_of(batch, all), s))
+    return rc;
+  CK(batch_copy(batch, z, P->N, wr, batch->MS, s));
+  return RSFDE_OK;
+}
+
+int rsfde_batch_step(rsfde_batch batch, const double* u_prev, const double* u_prev2,
+                     int32_t f_kind, const rsfde_solver_opts* opts, double* u_next,
+                     rsfde_stats* stats, void* stream) {
+  using namespace rsfde;
+  auto fail = [&](int code) {
+    if (batch && stats)
+      for (int m = 0; m < batch->B; ++m) finish(&stats[m], code, 0, 0, 0, 0);
+    return code;
+  };
+  if (!batch || !u_prev || !u_next || u_next == u_prev) return fail(RSFDE_EINVAL);
+  if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return fail(RSFDE_EINVAL);
+  Plan* P = &batch->plan->p;
+  if (!opts) return fail(RSFDE_EINVAL);
+  rsfde_solver_opts o = *opts;
+  if (o.restart < 1 || o.restart > (int)((batch->o_Z - batch->o_V) / P->ldv) - 1)
+    return fail(RSFDE_EINVAL);
+  if (o.max_iters < 1 || !(o.tol > 0.0) || !std::isfinite(o.tol) || o.reorth < -1 || o.reorth > 1)
+    return fail(RSFDE_EINVAL);
+  if (o.precision != RSFDE_FP64 && o.precision != RSFDE_FP32) return fail(RSFDE_EUNSUPPORTED);
+  if (o.precond != RSFDE_PRECOND_TAU || o.side != RSFDE_RIGHT || o.sstep > 1)
+    return fail(RSFDE_EUNSUPPORTED);
+  DeviceGuard g(P->dev);
+  if (!g.ok) return fail(RSFDE_EHIP);
+  hipStream_t s = pick(P, stream);
+  for (int m = 0; m < batch->B; ++m) batch->hs[m].flags = 0;
+  std::vector<int> all(batch->B);
+  for (int m = 0; m < batch->B; ++m) all[m] = m;
+  const Members mb = members_of(batch, all);
+  double* R = batch->region;
+  if (launch_rhs(u_prev, u_prev2, P->mask, P->dt, f_kind, nullptr, 0.0, R + batch->o_b,
+                 R + batch->o_x, P->N, RedWork{R + batch->o_part}, batch->hs_dev, s, mb, P->N) !=
+      hipSuccess)
+    return fail(RSFDE_EHIP);
+  const int rc = batch_solve(batch, &o, stats, s);
+  if (batch_copy(batch, u_next, P->N, R + batch->o_x, batch->MS, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(RSFDE_EHIP);
+  return rc;
+}
+
+int rsfde_batch_destroy(rsfde_batch batch) {
+  if (!batch) return RSFDE_OK;
+  {
+    rsfde::DeviceGuard g(batch->plan->p.dev);
+    (void)hipDeviceSynchronize();
+  }
+  delete batch;
+  return RSFDE_OK;
+}
+
+}  // extern "C"

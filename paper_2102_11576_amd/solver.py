@@ -190,3 +190,99 @@ def march_ensemble(plans, u0s, m, f_kind, opts, streams=None):
     sts = L.rsfde_march_ensemble([pl.handle for pl in plans], u0s, m, f_kind, opts, outs, works,
                                  streams)
     return outs, [StepStats(s.iters, s.restarts, s.relres, s.status) for s in sts]
+
+
+class RsfdeBatch:
+    """Owns one rsfde_batch: `count` independent members of one grid (shared
+    orders, mask, eta, dt; own kx, ky, fields and Krylov state), stepped
+    together (rsfde_batch_step).  Vectors are [count * N] FP64 tensors, member
+    after member."""
+
+    def __init__(self, n1, n2, box, alpha1, alpha2, kxs, kys, mask, eta, dt, max_restart=30,
+                 device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        if not isinstance(mask, torch.Tensor):
+            mask = torch.as_tensor(mask)
+        self.mask = mask.to(device=dev, dtype=torch.uint8).contiguous().reshape(-1)
+        self.n1, self.n2 = int(n1), int(n2)
+        self.count = len(kxs)
+        self.kxs, self.kys = [float(k) for k in kxs], [float(k) for k in kys]
+        self.device = dev
+        self.max_restart = int(max_restart)
+        with torch.cuda.device(dev):
+            self.handle = L.rsfde_batch_setup(self.n1, self.n2, box, alpha1, alpha2, kxs, kys,
+                                              self.mask, eta, dt, max_restart)
+
+    @classmethod
+    def from_workload(cls, w, kxs, kys, max_restart=None, device=None):
+        return cls(w.n1, w.n2, w.box, w.alpha1, w.alpha2, kxs, kys, torch.as_tensor(w.mask),
+                   w.eta, w.T / w.m, w.restart if max_restart is None else max_restart, device)
+
+    @property
+    def N(self):
+        return self.n1 * self.n2
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            L.rsfde_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def empty(self):
+        return torch.empty(self.count * self.N, dtype=torch.float64, device=self.device)
+
+    def set_coeffs(self, kxs, kys):
+        L.rsfde_batch_set_coeffs(self.handle, kxs, kys)
+        self.kxs, self.kys = [float(k) for k in kxs], [float(k) for k in kys]
+
+    def matvec(self, x, y=None):
+        y = self.empty() if y is None else y
+        L._check_vec(x, self.count * self.N, "x")
+        L._check_vec(y, self.count * self.N, "y")
+        L.rsfde_batch_matvec(self.handle, x, y)
+        return y
+
+    def precond(self, r, z=None, precision="fp64"):
+        z = self.empty() if z is None else z
+        L._check_vec(r, self.count * self.N, "r")
+        L._check_vec(z, self.count * self.N, "z")
+        L.rsfde_batch_precond_apply(self.handle, r, z, precision)
+        return z
+
+    def step(self, u_prev, u_prev2, f_kind, opts, u_next=None, check=True):
+        if opts.sstep > 1:
+            raise ValueError("batched solves run the one-vector form: build opts with sstep=0")
+        u_next = self.empty() if u_next is None else u_next
+        for t, nm in ((u_prev, "u_prev"), (u_next, "u_next")):
+            L._check_vec(t, self.count * self.N, nm)
+        if u_prev2 is not None:
+            L._check_vec(u_prev2, self.count * self.N, "u_prev2")
+        sts = L.rsfde_batch_step(self.handle, self.count, u_prev, u_prev2, f_kind, opts, u_next,
+                                 check=check)
+        return u_next, [StepStats(s.iters, s.restarts, s.relres, s.status) for s in sts]
+
+    def march(self, u0, m, f_kind, opts):
+        """m steps of every member from u0 ([count * N]).  Returns (u^m, per-step
+        lists of the members' iteration counts)."""
+        L._check_vec(u0, self.count * self.N, "u0")
+        bufs = [u0.clone(), self.empty(), self.empty()]
+        cur, prev = 0, None
+        iters = []
+        for _ in range(m):
+            nxt = [i for i in range(3) if i != cur and i != prev][0]
+            _, sts = self.step(bufs[cur], None if prev is None else bufs[prev], f_kind, opts,
+                               bufs[nxt])
+            iters.append([s.iters for s in sts])
+            prev, cur = cur, nxt
+        return bufs[cur], iters

@@ -80,6 +80,25 @@ def test_host_validation_fails_fast(lib):
     assert mv(C.byref(bad), 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -1
     over = rsfde_grid(2048, 15, 0.0, 1.0, 0.0, 1.0)
     assert mv(C.byref(over), 1.5, 1.5, 1, 1, fake, 1e-6, .1, fake, P(0x2000), None) == -7
+    # batched solves: host validation before any device call
+    DP = C.POINTER(C.c_double)
+    lib.rsfde_batch_setup.argtypes = [C.POINTER(P), C.POINTER(rsfde_grid), C.c_double, C.c_double,
+                                      C.c_int32, DP, DP, P, C.c_double, C.c_double, C.c_int32, P]
+    ks = (C.c_double * 40)(*([1.0] * 40))
+    kneg = (C.c_double * 2)(1.0, -1.0)
+    bs = lib.rsfde_batch_setup
+    assert bs(None, C.byref(g), 1.5, 1.5, 2, ks, ks, fake, 1e-6, .1, 20, None) == -1
+    assert bs(C.byref(h), C.byref(g), 1.5, 1.5, 0, ks, ks, fake, 1e-6, .1, 20, None) == -1
+    assert bs(C.byref(h), C.byref(g), 1.5, 1.5, 33, ks, ks, fake, 1e-6, .1, 20, None) == -7
+    assert bs(C.byref(h), C.byref(g), 1.5, 1.5, 2, ks, kneg, fake, 1e-6, .1, 20, None) == -1
+    assert bs(C.byref(h), C.byref(g), 1.5, 1.5, 2, None, ks, fake, 1e-6, .1, 20, None) == -1
+    g30 = rsfde_grid(30, 15, 0.0, 1.0, 0.0, 1.0)  # n1 + 1 not a power of two
+    assert bs(C.byref(h), C.byref(g30), 1.5, 1.5, 2, ks, ks, fake, 1e-6, .1, 20, None) == -7
+    assert h.value is None
+    for fn, args in (("rsfde_batch_matvec", (None, fake, fake, None)),
+                     ("rsfde_batch_precond_apply", (None, fake, fake, 0, None))):
+        getattr(lib, fn).argtypes = [P] * 3 + ([C.c_int32] if "precond" in fn else []) + [P]
+        assert getattr(lib, fn)(*args) == -1
     # calls on a NULL plan
     lib.rsfde_matvec.argtypes = [P, P, P, P]
     assert lib.rsfde_matvec(None, fake, fake, None) == -1
