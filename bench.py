@@ -153,7 +153,7 @@ def kernel_mode(args):
     plan.close()
 
 
-def cpu_baseline(w, gpu_iters_per_step):
+def cpu_baseline(w, gpu_iters_per_step, log=lambda m: None):
     """The oracle as it stands, timed on this host's cores on a bounded sample
     of the same workload.
 
@@ -180,6 +180,7 @@ def cpu_baseline(w, gpu_iters_per_step):
     t0 = time.perf_counter()
     _, its, _ = O.gmres(A, b, w.u0, w.restart, 1e-300, w.restart, Pi, "right")
     t_cycle = time.perf_counter() - t0
+    log(f"CPU oracle: one GMRES({w.restart}) cycle at {w.n1}^2 in {t_cycle:.1f} s")
     t_step = t_rhs + (gpu_iters_per_step / w.restart) * t_cycle
     # dense LU on the c1 shape (the survey's O1 tier), whole
     w1 = make_config("c1")
@@ -284,8 +285,9 @@ def configs_rates(log, sstep=10):
     steps, FP32 preconditioner inside FGMRES(20) tol 1e-8, s-step): forward
     march, then one backward pass (checkpointed forward + adjoint sweep, FP32
     preconditioner in both) for the gradient of L = ||u(T)||^2 with respect to
-    u0, kx and ky, checked by central differences (h = 1e-6, tol 1e-12) on two
-    seeded directions."""
+    u0, kx and ky, checked by central differences (h = 1e-4, tol 1e-10: the
+    residual's rounding floor at this stiffness is near 5e-11) on two seeded
+    directions."""
     import numpy as np
     import torch
     from paper_2102_11576_amd import RsfdePlan, make_opts
@@ -349,7 +351,9 @@ def configs_rates(log, sstep=10):
         torch.cuda.synchronize()
         r5["backward_pass_s"] = time.perf_counter() - t0
         log(f"c5 gradient (checkpointed forward + adjoint sweep): {r5['backward_pass_s']:.2f} s")
-        tight = make_opts(w.restart, 100000, 1e-12, "fp32", sstep=sstep)
+        # FD at tol 1e-10 (the residual's rounding floor at 4095^2 is near
+        # 5e-11) with h = 1e-4: noise ~ tol / h = 1e-6, truncation ~ h^2
+        tight = make_opts(w.restart, 100000, 1e-10, "fp32", sstep=0)
         g0, gkx, gky = grad(tight)
 
         def loss(uu0, kx, ky):
@@ -360,7 +364,7 @@ def configs_rates(log, sstep=10):
         for i in range(2):
             du, dkx, dky = fd_direction(w.u0.shape, i)
             dut = torch.as_tensor(du, device=dev).reshape(-1)
-            h = 1e-6
+            h = 1e-4
             fd = (loss(u0 + h * dut, w.kx + h * dkx, w.ky + h * dky)
                   - loss(u0 - h * dut, w.kx - h * dkx, w.ky - h * dky)) / (2 * h)
             an = float(torch.dot(g0, dut)) + gkx * dkx + gky * dky
@@ -654,8 +658,8 @@ def main():
     plan = RsfdePlan.from_workload(w, device=dev)
     u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
 
-    def timed_march(precision, steps, profile=False, sstep=args.sstep):
-        opts = make_opts(w.restart, 100000, w.tol, precision, sstep=sstep)
+    def timed_march(precision, steps, profile=False, sstep=args.sstep, zstore="fp64"):
+        opts = make_opts(w.restart, 100000, w.tol, precision, sstep=sstep, zstore=zstore)
         if W > 0:
             plan.march(u0, min(W, w.m), w.f_kind, opts)
         torch.cuda.synchronize()
@@ -721,13 +725,39 @@ def main():
         u32, it32, t32, _ = timed_march("fp32", K)
         log(f"fp32 preconditioner: {1e3 * t32 / K:.2f} ms/step, {np.mean(it32):.1f} iterations/step")
         d = float((u32 - u64).abs().max() / u64.abs().max())
-        # FP64 reference at tol 1e-12: both tol-1e-8 results against it
-        opts_t = make_opts(w.restart, 100000, 1e-12, "fp64", sstep=args.sstep)
-        u_t, it_t, _ = plan.march(u0, K, w.f_kind, opts_t)
+        # the preconditioned basis Z kept in FP32 (with either preconditioner)
+        zres = {}
+        for prec in ("fp64", "fp32"):
+            uz, itz, tz, _ = timed_march(prec, K, zstore="fp32")
+            zres[prec] = {"value": w.N * K / tz, "ms_per_step": 1e3 * tz / K,
+                          "gmres_iters_per_step": float(np.mean(itz)),
+                          "rel_err_inf_vs_fp64": float((uz - u64).abs().max() / u64.abs().max())}
+            log(f"{prec} preconditioner, Z in FP32: {1e3 * tz / K:.2f} ms/step, "
+                f"{np.mean(itz):.1f} iterations/step")
+        # Tight FP64 reference (one Arnoldi vector per step, two Gram-Schmidt
+        # passes) at tol 1e-10: at this stiffness the true residual b - Mx
+        # computed in FP64 carries a rounding floor of about eps sum_j |M_ij| |x_j|
+        # (sum_j |M_ij| ~ 3.5e5), i.e. about 4e-11 of ||b||, so 1e-12 and 1e-11
+        # are out of reach; the achieved relative residuals are reported.
+        TIGHT = 1e-10
+        opts_t = make_opts(w.restart, 3000, TIGHT, "fp64", sstep=0)
+        bufs = [u0.clone(), plan.empty(), plan.empty()]
+        cur, prv, it_t, rel_t = 0, None, [], []
+        for _ in range(K):
+            nxt = [i for i in range(3) if i != cur and i != prv][0]
+            _, st_t = plan.step(bufs[cur], None if prv is None else bufs[prv], w.f_kind, opts_t,
+                                bufs[nxt], check=False)
+            it_t.append(st_t.iters)
+            rel_t.append(st_t.relres)
+            prv, cur = cur, nxt
+            if len(it_t) % 8 == 0:
+                log(f"tight reference: step {len(it_t)}, {st_t.iters} iterations, relres {st_t.relres:.2e}")
         torch.cuda.synchronize()
+        u_t = bufs[cur]
         d64_t = float((u64 - u_t).abs().max() / u_t.abs().max())
         d32_t = float((u32 - u_t).abs().max() / u_t.abs().max())
-        log(f"vs FP64 at tol 1e-12: fp64 {d64_t:.2e}, fp32 {d32_t:.2e}")
+        log(f"vs FP64 at tol {TIGHT:g} (largest relative residual {max(rel_t):.2e}): "
+            f"fp64 {d64_t:.2e}, fp32 {d32_t:.2e}")
         # BF16 preconditioner: not supported at this stiffness.  Flexible GMRES
         # stalls from step 3 on (the BF16 rounding of each preconditioned
         # vector, about 6e-3 relative, is amplified by ||M|| ~ 1e5 in the next
@@ -741,9 +771,16 @@ def main():
         out["mixed"] = {
             "fp32": {"value": w.N * K / t32, "ms_per_step": 1e3 * t32 / K, "steps": K,
                      "gmres_iters_per_step": float(np.mean(it32)), "rel_err_inf_vs_fp64": d,
-                     "rel_err_inf_vs_fp64_tol_1e-12": d32_t},
-            "fp64_rel_err_inf_vs_fp64_tol_1e-12": d64_t,
-            "fp64_tol_1e-12_iters_per_step": float(np.mean(it_t)),
+                     "rel_err_inf_vs_fp64_tight": d32_t},
+            "zstore_fp32": {"note": "preconditioned basis Z stored in FP32 (rounded when "
+                                    "stored; M z formed from the stored vector)",
+                            "fp64_preconditioner": zres["fp64"], "fp32_preconditioner": zres["fp32"]},
+            "fp64_rel_err_inf_vs_fp64_tight": d64_t,
+            "fp64_tight": {"tol": TIGHT, "iters_per_step": float(np.mean(it_t)),
+                           "max_relres": float(max(rel_t)),
+                           "note": "tol 1e-12 (and 1e-11) is below the FP64 rounding floor of "
+                                   "the true residual at this stiffness (about eps "
+                                   "max_i sum_j |M_ij| ~ 4e-11)"},
             "bf16": {"supported": False,
                      "reason": "flexible GMRES stalls from step 3 on at this stiffness: the BF16 "
                                "rounding of each preconditioned vector (about 6e-3 relative) is "
@@ -819,7 +856,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(w, float(np.mean(it64)))
+        out["cpu_baseline"] = cpu_baseline(w, float(np.mean(it64)), log)
 
     plan.close()
     print(json.dumps(out))

@@ -64,6 +64,8 @@ extern "C" {
 #define RSFDE_F_DECAY 4    /* f = -u (with a source field: Example 1 of Section 5) */
 
 /* preconditioning side (rsfde_solver_opts.side) */
+#define RSFDE_ZSTORE_FP64 0
+#define RSFDE_ZSTORE_FP32 1
 #define RSFDE_RIGHT 0 /* flexible GMRES on M P^{-1}; stop on ||b - M x|| <= tol ||b|| */
 #define RSFDE_LEFT 1  /* GMRES on P^{-1} M; stop on the estimate of ||P^{-1}(b - M x)||
                          <= tol ||P^{-1} b||: the stopping rule of Section 5 */
@@ -92,6 +94,15 @@ typedef struct {
                         together (block Gram-Schmidt + Cholesky QR); same Krylov space,
                         about s times less basis traffic.  Grids with N < 4096 use the
                         one-vector form. */
+  int32_t zstore;    /* storage of the preconditioned basis Z of the flexible GMRES:
+                        RSFDE_ZSTORE_FP64 (default) or RSFDE_ZSTORE_FP32.  With FP32
+                        each z_j is rounded when stored and w_j = M z_j is formed from
+                        the stored vector, so the Arnoldi relation M Z = V H holds for
+                        the kept basis and the true-residual stop is unchanged; the
+                        basis reads of the solution update and the product's z reads
+                        halve.  Right side, sine-transform preconditioner (FP64 or
+                        FP32), two-dimensional plans with n1+1 and n2+1 powers of two
+                        (EUNSUPPORTED otherwise). */
 } rsfde_solver_opts;
 
 typedef struct {

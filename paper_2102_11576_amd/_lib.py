@@ -27,6 +27,7 @@ RSFDE_FP64, RSFDE_FP32, RSFDE_BF16 = 0, 1, 2
 RSFDE_PRECOND_TAU, RSFDE_PRECOND_NONE = 0, 1
 RSFDE_F_NONE, RSFDE_F_LOGISTIC, RSFDE_F_SIN, RSFDE_F_CUBIC, RSFDE_F_DECAY = 0, 1, 2, 3, 4
 RSFDE_RIGHT, RSFDE_LEFT = 0, 1
+RSFDE_ZSTORE_FP64, RSFDE_ZSTORE_FP32 = 0, 1
 
 PRECISIONS = {"fp64": RSFDE_FP64, "fp32": RSFDE_FP32, "bf16": RSFDE_BF16}
 
@@ -47,7 +48,7 @@ class rsfde_grid3(C.Structure):
 class rsfde_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("reorth", C.c_int32),
-                ("side", C.c_int32), ("sstep", C.c_int32)]
+                ("side", C.c_int32), ("sstep", C.c_int32), ("zstore", C.c_int32)]
 
 
 class rsfde_stats(C.Structure):
@@ -168,14 +169,16 @@ DEFAULT_SSTEP = 10
 
 
 def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="tau", reorth=0,
-              side="right", sstep=None):
+              side="right", sstep=None, zstore="fp64"):
     """reorth: 0 or 1 = two Gram-Schmidt passes (CGS2), -1 = one (one-vector
     form only).  side: "right" (flexible GMRES, true-residual stop) or "left"
     (the stopping rule of the paper's experiments).  sstep: 0/1 one Arnoldi
     vector per step, s >= 2 the s-step block form; None (default) picks the
     s-step form with s = 10 where it is supported (right side, sine-transform
     preconditioner in FP64 or FP32; the library itself takes the one-vector
-    form on grids below 4096 unknowns) and the one-vector form elsewhere."""
+    form on grids below 4096 unknowns) and the one-vector form elsewhere.
+    zstore: "fp64" or "fp32", the storage of the flexible GMRES's preconditioned
+    basis (FP32: rounded when stored; the product uses the stored vectors)."""
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pc = {"tau": RSFDE_PRECOND_TAU, "none": RSFDE_PRECOND_NONE}[precond] \
         if isinstance(precond, str) else int(precond)
@@ -183,8 +186,10 @@ def make_opts(restart=30, max_iters=10000, tol=1e-8, precision="fp64", precond="
     if sstep is None:
         ok = sd == RSFDE_RIGHT and pc == RSFDE_PRECOND_TAU and p in (RSFDE_FP64, RSFDE_FP32)
         sstep = DEFAULT_SSTEP if ok and int(restart) + 1 + DEFAULT_SSTEP <= 80 else 0
+    zs = {"fp64": RSFDE_ZSTORE_FP64, "fp32": RSFDE_ZSTORE_FP32}[zstore] \
+        if isinstance(zstore, str) else int(zstore)
     return rsfde_solver_opts(int(restart), int(max_iters), float(tol), p, pc, int(reorth), sd,
-                             int(sstep))
+                             int(sstep), zs)
 
 
 def rsfde_setup(n1, n2, box, alpha1, alpha2, kx, ky, mask, eta, dt, max_restart=30, stream=None):

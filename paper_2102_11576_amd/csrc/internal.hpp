@@ -84,11 +84,14 @@ hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* o
 // Column pass: out = coef * (C_y z) + (mode==0 ? t : 0) on `batch` [n2][n1]
 // slices, slice b at offset b * bstride of z, t and out.  tiled (mode 0, one
 // slice): t in the strip-tiled layout.
-hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
+// z32 (mode 0, tiled, one slice): z is a float array (the preconditioned
+// basis kept in FP32).
+hipError_t launch_mv_cols(int L, const void* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2,
                           double coef, int mode, hipStream_t s, int batch = 1,
                           size_t bstride = 0, bool tiled = false,
-                          const Members& mb = Members::one(), const double* mk = nullptr);
+                          const Members& mb = Members::one(), const double* mk = nullptr,
+                          bool z32 = false);
 
 // Sine-transform preconditioner, three passes; T = float or double internally.
 // tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q is
@@ -133,14 +136,15 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
 // t = (1 + dpen (1 - mask)) z + coef (C_x z) - theta sub (sub may be NULL);
 // tiled: P1/P2 pairs in row segments, t strip-tiled over n1 columns.
 // Batched: P1, P2, z, t, sub advance by the member offset; with mk given,
-// coef = -mk[offset].
+// coef = -mk[offset].  z32: z is stored in FP32 (a float array; tiled only),
+// and the product uses the stored (rounded) values.
 template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
-                                 const uint8_t* mask, double* z, double* t, const void* twT,
+                                 const uint8_t* mask, void* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
                                  hipStream_t s, const Members& mb = Members::one(),
-                                 const double* mk = nullptr);
+                                 const double* mk = nullptr, bool z32 = false);
 
 // Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
 // power of two): T internals, tables chn (n entries) and khat (L entries, in
@@ -198,14 +202,16 @@ hipError_t launch_axpy_givens(const double* V, size_t ldv, int nv, const double*
 // x += sum_{i<jc} y_i Z_i with R y = g; scaled = true multiplies y_i by
 // vscale[i] (Z = the unnormalised basis V: left preconditioning).
 // Batched: member slot k uses jc[k] vectors (jcs given; jc = their maximum).
-hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
+// z32: Z is a float array (vector i at Z + i * ldz floats).
+hipError_t launch_update(const void* Z, size_t ldz, int jc, double* x, size_t N,
                          KrylovState* ks, bool scaled, hipStream_t s,
-                         const Members& mb = Members::one(), const int32_t* jcs = nullptr);
+                         const Members& mb = Members::one(), const int32_t* jcs = nullptr,
+                         bool z32 = false);
 // x += sum_{i<jc} c_i Z_i with the coefficients c given (device array).
 // As launch_update with the coefficients y given on the host (jc doubles,
 // passed to the kernels as arguments).
-hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                              const double* c_host, hipStream_t s);
+hipError_t launch_update_coef(const void* Z, size_t ldz, int jc, double* x, size_t N,
+                              const double* c_host, hipStream_t s, bool z32 = false);
 
 // s-step blocks (krylov_block.hip).  G (pinned, device-visible, [nr][16]) =
 // [V_0 .. V_{nr-1}]^T [V_{m1} .. V_{m1+s-1}]; gpart holds

@@ -102,9 +102,9 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu
 // compile-time mode keeps the epilogue's loads free of per-element branches,
 // which measured 10 % faster at n = 2047.
 // --------------------------------------------------------------------------
-template <int L, int MODE, bool TT>
+template <int L, int MODE, bool TT, typename ZT = double>
 __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu(4))) void k_mv_cols(
-    const double* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
+    const ZT* __restrict__ z, const double* __restrict__ t, double* __restrict__ out,
     const double* __restrict__ sym, const cpx<double>* __restrict__ tw, int n1, int n2,
     double coef, size_t bstride, const Members mb, const double* __restrict__ mk) {
   using C = MvCfg<L>;
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
     const bool in = p < n2;
-    reg[e].re = (va && in) ? z[(size_t)p * n1 + ca] : 0.0;
-    reg[e].im = (vb && in) ? z[(size_t)p * n1 + cb] : 0.0;
+    reg[e].re = (va && in) ? (double)z[(size_t)p * n1 + ca] : 0.0;
+    reg[e].im = (vb && in) ? (double)z[(size_t)p * n1 + cb] : 0.0;
   });
   double* my = lds + b;  // regions interleaved (stride BC)
   fft_forward<double, F, true, C::BC>(reg, tau, tw, my);
@@ -186,10 +186,11 @@ static hipError_t mv_rows_impl(const double* z, const uint8_t* mask, double* out
 }
 
 template <int L>
-static hipError_t mv_cols_impl(const double* z, const double* t, double* out, const double* sym,
+static hipError_t mv_cols_impl(const void* zv, const double* t, double* out, const double* sym,
                                const void* tw, int n1, int n2, double coef, int mode, hipStream_t s,
                                int batch, size_t bstride, bool tiled, const Members& mb,
-                               const double* mk) {
+                               const double* mk, bool z32) {
+  const double* z = (const double*)zv;
   using C = MvCfg<L>;
   const int pairs = (n1 + 1) / 2;
   const int blocks = (pairs + C::BC - 1) / C::BC;
@@ -198,6 +199,12 @@ static hipError_t mv_cols_impl(const double* z, const double* t, double* out, co
   if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   const dim3 grid(blocks, batch, mb.n), thr(C::THR_C);
   const cpx<double>* twc = (const cpx<double>*)tw;
+  if (z32) {
+    if (mode != 0 || !tiled) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mv_cols<L, 0, true, float>), grid, thr, 0, s, (const float*)zv, t, out,
+                       sym, twc, n1, n2, coef, bstride, mb, mk);
+    return hipGetLastError();
+  }
   if (mode != 0)
     hipLaunchKernelGGL((k_mv_cols<L, 1, false>), grid, thr, 0, s, z, t, out, sym, twc, n1, n2,
                        coef, bstride, mb, mk);
@@ -229,15 +236,15 @@ hipError_t launch_mv_rows(int L, const double* z, const uint8_t* mask, double* o
   }
 }
 
-hipError_t launch_mv_cols(int L, const double* z, const double* t, double* out,
+hipError_t launch_mv_cols(int L, const void* z, const double* t, double* out,
                           const double* sym, const void* tw, int n1, int n2, double coef,
                           int mode, hipStream_t s, int batch, size_t bstride, bool tiled,
-                          const Members& mb, const double* mk) {
+                          const Members& mb, const double* mk, bool z32) {
   switch (L) {
 #define X(LL)                                                                                   \
   case LL:                                                                                      \
     return mv_cols_impl<LL>(z, t, out, sym, tw, n1, n2, coef, mode, s, batch, bstride, tiled, mb, \
-                            mk);
+                            mk, z32);
     RSFDE_L_CASES(X)
 #undef X
     default:

@@ -18,8 +18,8 @@ struct JcList {
   int32_t jc[kMaxBatch];
 };
 
-template <int NV>
-__global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict__ Z, size_t ldz,
+template <int NV, typename ZT = double>
+__global__ __launch_bounds__(kRedThreads) void k_update(const ZT* __restrict__ Z, size_t ldz,
                                                         double* __restrict__ x, size_t N,
                                                         const KrylovState* __restrict__ ks,
                                                         int v0, int jc, bool scaled, bool given,
@@ -59,8 +59,15 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
        i += (size_t)gridDim.x * blockDim.x) {
     double2 z[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      z[v] = reinterpret_cast<const double2*>(Z + (size_t)(v < nvm ? v : 0) * ldz)[i];
+    for (int v = 0; v < NV; ++v) {
+      const ZT* zp = Z + (size_t)(v < nvm ? v : 0) * ldz;
+      if constexpr (sizeof(ZT) == 8) {
+        z[v] = reinterpret_cast<const double2*>(zp)[i];
+      } else {
+        const float2 f = reinterpret_cast<const float2*>(zp)[i];
+        z[v] = double2{(double)f.x, (double)f.y};
+      }
+    }
     double2 s = x2[i];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -73,30 +80,32 @@ __global__ __launch_bounds__(kRedThreads) void k_update(const double* __restrict
     double s = x[N - 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      if (v < nvm) s += c[v] * Z[(size_t)v * ldz + N - 1];
+      if (v < nvm) s += c[v] * (double)Z[(size_t)v * ldz + N - 1];
     x[N - 1] = s;
   }
 }
 
-using UpdateFn = void (*)(const double*, size_t, double*, size_t, const KrylovState*, int, int,
+using UpdateFn = void (*)(const void*, size_t, double*, size_t, const KrylovState*, int, int,
                           bool, bool, const UpdateCoef&, const Members&, const JcList&, dim3,
                           hipStream_t);
-template <int NV>
-static void run_update(const double* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
+template <int NV, typename ZT>
+static void run_update(const void* Z, size_t ldz, double* x, size_t N, const KrylovState* ks,
                        int v0, int jc, bool scaled, bool given, const UpdateCoef& cg,
                        const Members& mb, const JcList& jl, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_update<NV>, g, dim3(kRedThreads), 0, s, Z, ldz, x, N, ks, v0, jc, scaled,
-                     given, cg, mb, jl);
+  hipLaunchKernelGGL((k_update<NV, ZT>), g, dim3(kRedThreads), 0, s, (const ZT*)Z, ldz, x, N, ks,
+                     v0, jc, scaled, given, cg, mb, jl);
 }
-template <int... I>
+template <typename ZT, int... I>
 static constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
-  return {&run_update<I + 1>...};
+  return {&run_update<I + 1, ZT>...};
 }
-static const auto kUpdate = update_table(std::make_integer_sequence<int, kChunk>{});
+static const auto kUpdate = update_table<double>(std::make_integer_sequence<int, kChunk>{});
+static const auto kUpdate32 = update_table<float>(std::make_integer_sequence<int, kChunk>{});
 
-hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t N,
+hipError_t launch_update(const void* Z, size_t ldz, int jc, double* x, size_t N,
                          KrylovState* ks, bool scaled, hipStream_t s, const Members& mb,
-                         const int32_t* jcs) {
+                         const int32_t* jcs, bool z32) {
+  const size_t zb = z32 ? sizeof(float) : sizeof(double);
   if (jc <= 0) return hipSuccess;
   if (jc > kMaxRestart) return hipErrorInvalidValue;
   if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
@@ -108,24 +117,27 @@ hipError_t launch_update(const double* Z, size_t ldz, int jc, double* x, size_t 
   }
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, ks, v0, jc, scaled, false, none, mb, jl,
-                   dim3(stream_blocks(N), mb.n), s);
+    (z32 ? kUpdate32 : kUpdate)[n - 1]((const char*)Z + (size_t)v0 * ldz * zb, ldz, x, N, ks, v0,
+                                       jc, scaled, false, none, mb, jl,
+                                       dim3(stream_blocks(N), mb.n), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_update_coef(const double* Z, size_t ldz, int jc, double* x, size_t N,
-                              const double* c_host, hipStream_t s) {
+hipError_t launch_update_coef(const void* Z, size_t ldz, int jc, double* x, size_t N,
+                              const double* c_host, hipStream_t s, bool z32) {
+  const size_t zb = z32 ? sizeof(float) : sizeof(double);
   if (jc <= 0) return hipSuccess;
   if (jc > kMaxRestart) return hipErrorInvalidValue;
   UpdateCoef cg{};
   for (int i = 0; i < jc; ++i) cg.v[i] = c_host[i];
   for (int v0 = 0; v0 < jc; v0 += kChunk) {
     const int n = jc - v0 < kChunk ? jc - v0 : kChunk;
-    kUpdate[n - 1](Z + (size_t)v0 * ldz, ldz, x, N, nullptr, v0, jc, false, true, cg,
-                   Members::one(), JcList{}, dim3(stream_blocks(N)), s);
+    (z32 ? kUpdate32 : kUpdate)[n - 1]((const char*)Z + (size_t)v0 * ldz * zb, ldz, x, N,
+                                       nullptr, v0, jc, false, true, cg, Members::one(),
+                                       JcList{}, dim3(stream_blocks(N)), s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -11,10 +11,10 @@ template hipError_t launch_pc_rows_inv<double>(int, const double*, const double*
                                             const uint8_t*, double*, const void*, int, int,
                                             bool, hipStream_t, const Members&);
 template hipError_t launch_pc_rows_inv_mv<double>(int, const double*, const double*,
-                                             const uint8_t*, double*, double*, const void*,
+                                             const uint8_t*, void*, double*, const void*,
                                              const void*, const double*, double, double,
                                              const double*, double, int, int, bool, hipStream_t,
-                                             const Members&, const double*);
+                                             const Members&, const double*, bool);
 template hipError_t launch_dst_cols<double>(int, const double*, const double*, double*, double*, const void*, int,
                                           int, int, int, int, int, size_t, hipStream_t);
 }  // namespace rsfde

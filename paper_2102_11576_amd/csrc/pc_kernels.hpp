@@ -437,11 +437,14 @@ __global__ __launch_bounds__(PcCfg<L>::THR_R) void k_pc_rows_inv(
 // z is placed at positions 1..n1 of the convolution (where pass C leaves it),
 // a circular shift that the convolution carries to its output.
 // --------------------------------------------------------------------------
-template <typename T, int L, bool TL>
+// ZT: the storage type of z.  With ZT = float (the preconditioned basis kept
+// in FP32) z is rounded when stored and the product uses the rounded values,
+// so that w = M z holds for the z that is kept.
+template <typename T, int L, bool TL, typename ZT = double>
 __global__ __launch_bounds__(PcCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu(4)))
 void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
                       const uint8_t* __restrict__ mask,
-                      double* __restrict__ z, double* __restrict__ t,
+                      ZT* __restrict__ z, double* __restrict__ t,
                       const cpx<T>* __restrict__ twT, const cpx<double>* __restrict__ tw64,
                       const double* __restrict__ sym, double coef, double dpen,
                       const double* __restrict__ sub, double theta, int n1, int n2,
@@ -472,7 +475,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     const T* P1h = P1;
     const T* P2h = P2;
     const cpx<T>* twh = twT;
-    double* zh = z;
+    ZT* zh = z;
     const uint8_t* mh = mask;
     int th = tau;
     asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
@@ -493,8 +496,8 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
       double zv = 0.0;
       if (vr && p >= 1 && p <= n1) {
         const size_t i = (size_t)r * n1 + (p - 1);
-        zv = mh[i] ? (double)reg[e].re : (double)reg[e].im;
-        zh[i] = zv;
+        zv = (double)(ZT)(mh[i] ? (double)reg[e].re : (double)reg[e].im);
+        zh[i] = (ZT)zv;
       }
       if (h == 1) zb[e] = zv;
     });
@@ -507,7 +510,7 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     constexpr int e = decltype(ee)::value;
     const int p = F::pos(0, tau, e);
     const bool in = p >= 1 && p <= n1;
-    reg[e].re = (va && in) ? z[(size_t)ra * n1 + (p - 1)] : 0.0;
+    reg[e].re = (va && in) ? (double)z[(size_t)ra * n1 + (p - 1)] : 0.0;
     reg[e].im = zb[e];
   });
   fft_forward<double, F>(reg, tau, tw64, my);
@@ -525,13 +528,13 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
     if (p >= 1 && p <= n1) {
       if (va) {
         const size_t i = (size_t)ra * n1 + (p - 1);
-        double v = reg[e].re + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        double v = reg[e].re + (1.0 + dpen * (double)(1 - mask[i])) * (double)z[i];
         if (sub) v -= theta * sub[i];
         t[TL ? tile_index(ra, p - 1, hp) : i] = v;
       }
       if (vb) {
         const size_t i = (size_t)rb * n1 + (p - 1);
-        double v = reg[e].im + (1.0 + dpen * (double)(1 - mask[i])) * z[i];
+        double v = reg[e].im + (1.0 + dpen * (double)(1 - mask[i])) * (double)z[i];
         if (sub) v -= theta * sub[i];
         t[TL ? tile_index(rb, p - 1, hp) : i] = v;
       }
@@ -580,7 +583,7 @@ static hipError_t pc_rows_inv_impl(const T* P1, const T* P2,
 
 template <typename T, int L, bool TL>
 static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
-                                      const uint8_t* mask, double* z, double* t, const void* twT,
+                                      const uint8_t* mask, void* z, bool z32, double* t, const void* twT,
                                       const void* tw64, const double* sym, double coef,
                                       double dpen, const double* sub, double theta, int n1,
                                       int n2, hipStream_t s, const Members& mb, const double* mk) {
@@ -588,9 +591,18 @@ static hipError_t pc_rows_inv_mv_impl(const T* P1, const T* P2,
   const int pairs = (n2 + 1) / 2;
   const int blocks = (pairs + C::BR - 1) / C::BR;
   if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_R), 0, s, P1,
-                     P2, mask, z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym, coef, dpen,
-                     sub, theta, n1, n2, mb, mk);
+  if (z32) {
+    if constexpr (TL)
+      hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL, float>), dim3(blocks, 1, mb.n), dim3(C::THR_R),
+                         0, s, P1, P2, mask, (float*)z, t, (const cpx<T>*)twT,
+                         (const cpx<double>*)tw64, sym, coef, dpen, sub, theta, n1, n2, mb, mk);
+    else
+      return hipErrorInvalidValue;  // FP32 storage of z: two-dimensional (tiled) plans only
+  } else {
+    hipLaunchKernelGGL((k_pc_rows_inv_mv<T, L, TL>), dim3(blocks, 1, mb.n), dim3(C::THR_R), 0, s, P1,
+                       P2, mask, (double*)z, t, (const cpx<T>*)twT, (const cpx<double>*)tw64, sym,
+                       coef, dpen, sub, theta, n1, n2, mb, mk);
+  }
   return hipGetLastError();
 }
 
@@ -677,17 +689,17 @@ hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
 
 template <typename T>
 hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
-                                 const uint8_t* mask, double* z, double* t, const void* twT,
+                                 const uint8_t* mask, void* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
-                                 hipStream_t s, const Members& mb, const double* mk) {
+                                 hipStream_t s, const Members& mb, const double* mk, bool z32) {
   switch (L) {
 #define X(LL)                                                                                    \
   case LL:                                                                                       \
-    return tiled ? pc_rows_inv_mv_impl<T, LL, true>(P1, P2, mask, z, t, twT, tw64, sym, coef,    \
-                                                    dpen, sub, theta, n1, n2, s, mb, mk)         \
-                 : pc_rows_inv_mv_impl<T, LL, false>(P1, P2, mask, z, t, twT, tw64, sym, coef,   \
-                                                     dpen, sub, theta, n1, n2, s, mb, mk);
+    return tiled ? pc_rows_inv_mv_impl<T, LL, true>(P1, P2, mask, z, z32, t, twT, tw64, sym,     \
+                                                    coef, dpen, sub, theta, n1, n2, s, mb, mk)   \
+                 : pc_rows_inv_mv_impl<T, LL, false>(P1, P2, mask, z, z32, t, twT, tw64, sym,    \
+                                                     coef, dpen, sub, theta, n1, n2, s, mb, mk);
     RSFDE_LD_CASES(X)
 #undef X
     default:

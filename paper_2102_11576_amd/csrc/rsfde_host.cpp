@@ -518,9 +518,10 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
 // preconditioner's last pass and the matrix-vector row pass run as one kernel
 // when n1 + 1 and n2 + 1 are powers of two (FP64 / FP32 internals); otherwise
 // the two operators run one after the other.
-int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, double* w,
+int precond_matvec_impl(Plan* P, const double* v, const double* sig, void* zv, double* w,
                         int precision, hipStream_t s, const double* sub = nullptr,
-                        double theta = 0.0) {
+                        double theta = 0.0, bool z32 = false) {
+  double* z = (double*)zv;  // a float array when z32 (fused two-dimensional path only)
   if (P->is3d) {
     if (precision == RSFDE_FP64)
       return precond3<double>(P, v, sig, z, P->tw64, P->lamc64, P->lamz64, s, w, sub, theta);
@@ -530,6 +531,7 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
   }
   const bool fused = P->Ldx && P->Ldy && P->Ldx == P->Lcx &&
                      (precision == RSFDE_FP64 || precision == RSFDE_FP32);
+  if (z32 && !fused) return RSFDE_EUNSUPPORTED;
   if (!fused) {
     int rc = precond_impl(P, v, sig, z, precision, s);
     if (rc) return rc;
@@ -537,7 +539,7 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
   }
   const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
   const double N = (double)P->N, S = (double)(P->n1 + 1) * (double)P->n2;
-  const double extra = sub ? 8.0 * N : 0.0;
+  const double extra = (sub ? 8.0 * N : 0.0) - (z32 ? 4.0 * N : 0.0);
   if (precision == RSFDE_FP64) {
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
     {
@@ -553,7 +555,8 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
       ProfScope ps(P, s, kCatPcInvMv, 16.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mask, z, P->t,
                                        P->tw64[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
-                                       sub, theta, P->n1, P->n2, true, s));
+                                       sub, theta, P->n1, P->n2, true, s, Members::one(), nullptr,
+                                       z32));
     }
   } else {
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
@@ -570,13 +573,14 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, double* z, 
       ProfScope ps(P, s, kCatPcInvMv, 8.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mask, z, P->t,
                                       P->tw32[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
-                                      sub, theta, P->n1, P->n2, true, s));
+                                      sub, theta, P->n1, P->n2, true, s, Members::one(), nullptr,
+                                      z32));
     }
   }
   {
-    ProfScope ps(P, s, kCatMvCols, 24.0 * N);
+    ProfScope ps(P, s, kCatMvCols, (z32 ? 20.0 : 24.0) * N);
     CK(launch_mv_cols(P->Lcy, z, P->t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, -P->ky, 0, s, 1,
-                      0, true));
+                      0, true, Members::one(), nullptr, z32));
   }
   return RSFDE_OK;
 }
@@ -592,6 +596,14 @@ int validate_opts(Plan* P, const rsfde_solver_opts* o) {
   if (o->reorth < -1 || o->reorth > 1) return RSFDE_EINVAL;
   if (o->side != RSFDE_RIGHT && o->side != RSFDE_LEFT) return RSFDE_EINVAL;
   if (o->sstep < 0 || o->sstep > 16) return RSFDE_EINVAL;
+  if (o->zstore != RSFDE_ZSTORE_FP64 && o->zstore != RSFDE_ZSTORE_FP32) return RSFDE_EINVAL;
+  if (o->zstore == RSFDE_ZSTORE_FP32) {
+    // the preconditioned basis in FP32: the fused two-dimensional path only
+    const bool fused = !P->is3d && P->Ldx && P->Ldy && P->Ldx == P->Lcx;
+    if (!fused || o->precond != RSFDE_PRECOND_TAU || o->side != RSFDE_RIGHT ||
+        o->precision == RSFDE_BF16)
+      return RSFDE_EUNSUPPORTED;
+  }
   if (o->sstep >= 2) {
     if (o->precond != RSFDE_PRECOND_TAU || o->side != RSFDE_RIGHT) return RSFDE_EUNSUPPORTED;
     if (o->restart + 1 + o->sstep > 16 * kGramMaxTiles) return RSFDE_EUNSUPPORTED;
@@ -690,7 +702,10 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
         wv = zj;
       } else {  // z_j = P_hat^{-1} v_j, w = M z_j
         if (tau) {
-          rc = precond_matvec_impl(P, vj, sig, zj, P->w, o->precision, s);
+          void* zs = o->zstore == RSFDE_ZSTORE_FP32 ? (void*)((float*)P->Z + (size_t)j * ld)
+                                                    : (void*)zj;
+          rc = precond_matvec_impl(P, vj, sig, zs, P->w, o->precision, s, nullptr, 0.0,
+                                   o->zstore == RSFDE_ZSTORE_FP32);
           if (rc) return finish(st, rc, total, cycles, beta, bnorm);
         } else {
           {
@@ -745,7 +760,8 @@ int solve_core(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats* st, 
     const double est = vread(&hs->est[jc - 1]);
     {
       ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
-      CK(launch_update(left ? P->V : P->Z, ld, jc, x, N, P->ks, left, s));
+      CK(launch_update(left ? P->V : P->Z, ld, jc, x, N, P->ks, left, s, Members::one(), nullptr,
+                       !left && o->zstore == RSFDE_ZSTORE_FP32));
     }
     total += jc;
     if (left && est <= thresh) {  // stop on the preconditioned estimate
@@ -934,9 +950,10 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
       W[(size_t)m * RS + m] = 1.0;  // q_m is itself the first direction of the block
       for (int i = 0; i < ss; ++i) {
         double* ui = P->V + (size_t)(m + i) * ld;
-        double* zi = P->Z + (size_t)(m + i) * ld;
+        void* zi = o->zstore == RSFDE_ZSTORE_FP32 ? (void*)((float*)P->Z + (size_t)(m + i) * ld)
+                                                  : (void*)(P->Z + (size_t)(m + i) * ld);
         rc = precond_matvec_impl(P, ui, nullptr, zi, P->V + (size_t)(m + i + 1) * ld, o->precision,
-                                 s, ui, theta);
+                                 s, ui, theta, o->zstore == RSFDE_ZSTORE_FP32);
         if (rc) return finish_ev(st, events, rc, total, cycles, beta, bnorm);
       }
       const int nq = m + 1;
@@ -1098,7 +1115,7 @@ int solve_core_sstep(Plan* P, double* x, const rsfde_solver_opts* o, rsfde_stats
     }
     {
       ProfScope ps(P, s, kCatUpdate, 8.0 * (jc + 2) * (double)N);
-      CK(launch_update_coef(P->Z, ld, jc, x, N, cz.data(), s));
+      CK(launch_update_coef(P->Z, ld, jc, x, N, cz.data(), s, o->zstore == RSFDE_ZSTORE_FP32));
     }
     total += jc;
   }
@@ -2063,7 +2080,8 @@ int rsfde_batch_step(rsfde_batch batch, const double* u_prev, const double* u_pr
   if (o.max_iters < 1 || !(o.tol > 0.0) || !std::isfinite(o.tol) || o.reorth < -1 || o.reorth > 1)
     return fail(RSFDE_EINVAL);
   if (o.precision != RSFDE_FP64 && o.precision != RSFDE_FP32) return fail(RSFDE_EUNSUPPORTED);
-  if (o.precond != RSFDE_PRECOND_TAU || o.side != RSFDE_RIGHT || o.sstep > 1)
+  if (o.precond != RSFDE_PRECOND_TAU || o.side != RSFDE_RIGHT || o.sstep > 1 ||
+      o.zstore != RSFDE_ZSTORE_FP64)
     return fail(RSFDE_EUNSUPPORTED);
   DeviceGuard g(P->dev);
   if (!g.ok) return fail(RSFDE_EHIP);

@@ -131,3 +131,35 @@ def test_fd_check_differentiation_workload(sstep):
             an = float(torch.dot(g0, dut)) + gkx * dkx + gky * dky
             worst = max(worst, abs(fd - an) / max(abs(an), 1e-300))
     assert worst <= 1e-5, worst
+
+
+def test_c5_adjoint_on_two_steps():
+    """The 4095^2 hexagon configuration's backward pass (FP32 preconditioner
+    in forward and adjoint solves, f = u - u^3, L = ||u(T)||^2) on its first
+    two steps: the gradient against central differences on one seeded
+    direction.  tol 1e-10 (the true residual's FP64 rounding floor at this
+    stiffness is near 5e-11) and h = 1e-4: FD noise ~ 2 tol / h = 2e-6
+    relative; bar 1e-4."""
+    w = make_config("c5", m=2)
+    opts = make_opts(w.restart, 100000, 1e-10, "fp32", sstep=0)
+    with RsfdePlan.from_workload(w) as pl:
+        u0 = _t(w.u0)
+        x0 = u0.clone().requires_grad_(True)
+        tkx = torch.tensor(w.kx, dtype=torch.float64, device=DEV, requires_grad=True)
+        tky = torch.tensor(w.ky, dtype=torch.float64, device=DEV, requires_grad=True)
+        uT = RsfdeMarch.apply(x0, tkx, tky, pl, w.m, w.f_kind, opts)
+        (uT * uT).sum().backward()
+        g0, gkx, gky = x0.grad, float(tkx.grad), float(tky.grad)
+
+        def loss(uu0, kx, ky):
+            pl.set_coeffs(kx, ky)
+            u, _, _ = pl.march(uu0, w.m, w.f_kind, opts)
+            return float((u * u).sum())
+
+        du, dkx, dky = fd_direction(w.u0.shape, 0)
+        dut = _t(du)
+        h = 1e-4
+        fd = (loss(u0 + h * dut, w.kx + h * dkx, w.ky + h * dky)
+              - loss(u0 - h * dut, w.kx - h * dkx, w.ky - h * dky)) / (2 * h)
+    an = float(torch.dot(g0, dut)) + gkx * dkx + gky * dky
+    assert abs(fd - an) <= 1e-4 * abs(an), (fd, an)

@@ -121,3 +121,60 @@ def test_sstep_iteration_cap_and_nonfinite_input():
         bad[17] = float("nan")
         _, st = pl.step(bad, None, w.f_kind, make_opts(30, 100, 1e-8, sstep=4), check=False)
         assert st.status == rsfde._lib.RSFDE_ENONFINITE
+
+
+@pytest.mark.parametrize("s,precision", [(0, "fp64"), (8, "fp64"), (0, "fp32"), (8, "fp32")])
+def test_fp32_basis_storage_matches_dense_solve(s, precision):
+    """The preconditioned basis kept in FP32 (zstore): each z_j is rounded when
+    stored and M z_j is formed from the stored vector, so the flexible GMRES
+    still stops on the FP64 true residual and meets the dense solution's bar.
+    127 x 63 (n + 1 powers of two, the fused pass; 8001 unknowns, above the
+    s-step floor), the c4 orders on an ellipse."""
+    from workloads.configs import domain_mask, _ellipse
+    w = make_config("c4", n=127)
+    box = (0.0, 1.0, 0.0, 0.5)
+    mask = domain_mask(127, 63, box, _ellipse(0.5, 0.25, 0.4, 0.2, 10.0))
+    p = O.Problem(127, 63, box, w.alpha1, w.alpha2, 1.1, 0.8, w.eta, 1.0 / 32, mask)
+    b = np.random.default_rng(s + 3).standard_normal(p.n1 * p.n2)
+    x_ref = np.linalg.solve(O.dense_M(p), b)
+    with RsfdePlan(p.n1, p.n2, p.box, p.alpha1, p.alpha2, p.kx, p.ky, torch.as_tensor(p.mask),
+                   p.eta, p.dt) as pl:
+        x = torch.zeros(p.n1 * p.n2, dtype=torch.float64, device=DEV)
+        x, st = pl.solve(_t(b), x, make_opts(30, 100000, 1e-12, precision, sstep=s, zstore="fp32"))
+        x = x.cpu().numpy()
+    r = b - O.matvec(p, x.reshape(p.n2, p.n1)).ravel()
+    assert np.linalg.norm(r) <= 1.05e-12 * np.linalg.norm(b), st
+    assert np.abs(x - x_ref).max() <= 1e-10 * np.abs(x_ref).max(), st
+
+
+@pytest.mark.parametrize("s", [0, 10])
+def test_fp32_basis_storage_full_size_2047(s):
+    """Two steps at 2047^2 with the basis in FP32: the oracle recomputes the
+    second step's true residual."""
+    w = make_config("c3")
+    p = O.problem_from_workload(w)
+    opts = make_opts(w.restart, 100000, w.tol, sstep=s, zstore="fp32")
+    with RsfdePlan.from_workload(w) as pl:
+        u0 = _t(w.u0)
+        u1, _ = pl.step(u0, None, w.f_kind, opts)
+        u2, st = pl.step(u1, u0, w.f_kind, opts)
+        a1 = u1.cpu().numpy().reshape(w.n2, w.n1)
+        a2 = u2.cpu().numpy().reshape(w.n2, w.n1)
+    b = O.rhs(p, a1, w.f_kind)
+    r = b - O.matvec_fast(p, a2)
+    assert np.linalg.norm(r) <= (w.tol + 1e-12) * np.linalg.norm(b)
+    assert st.relres <= w.tol
+
+
+def test_fp32_basis_storage_rejected_where_unsupported():
+    w = make_config("c4", n=71, m=1)
+    with RsfdePlan.from_workload(w) as pl:
+        for kw in (dict(side="left"), dict(precond="none"), dict(precision="bf16")):
+            with pytest.raises(rsfde.RsfdeError) as ei:
+                pl.step(_t(w.u0), None, w.f_kind, make_opts(30, 100, 1e-8, zstore="fp32", **kw))
+            assert ei.value.code == rsfde._lib.RSFDE_EUNSUPPORTED
+    w2 = make_config("c4", n=70, m=1)   # n + 1 not a power of two: no fused pass
+    with RsfdePlan.from_workload(w2) as pl:
+        with pytest.raises(rsfde.RsfdeError) as ei:
+            pl.step(_t(w2.u0), None, w2.f_kind, make_opts(30, 100, 1e-8, zstore="fp32"))
+        assert ei.value.code == rsfde._lib.RSFDE_EUNSUPPORTED
