@@ -96,7 +96,7 @@ constexpr bool exchange_in_wave() {
 // rewrites the positions it reads (the fences keep the compiler from
 // reordering the LDS accesses).
 template <typename T, class F, int TF, int TT, int ST = 1, int TW = 0>
-__device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds) {
+__device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds, bool act = true) {
   constexpr bool wave_local = TW > 0 && exchange_in_wave<F, TF, TT, TW>();
   auto sync = [] {
     if constexpr (wave_local) {
@@ -106,13 +106,15 @@ __device__ __forceinline__ void lds_exchange(cpx<T>* reg, int tau, T* lds) {
       __syncthreads();
     }
   };
-  lds_put<T, F, TF, ST>(reg, tau, lds, false);
+  // act = false: a thread with no transform of its own still takes part in
+  // every block barrier (the block's other transforms need them).
+  if (act) lds_put<T, F, TF, ST>(reg, tau, lds, false);
   sync();
-  lds_get<T, F, TT, ST>(reg, tau, lds, false);
+  if (act) lds_get<T, F, TT, ST>(reg, tau, lds, false);
   sync();
-  lds_put<T, F, TF, ST>(reg, tau, lds, true);
+  if (act) lds_put<T, F, TF, ST>(reg, tau, lds, true);
   sync();
-  lds_get<T, F, TT, ST>(reg, tau, lds, true);
+  if (act) lds_get<T, F, TT, ST>(reg, tau, lds, true);
   sync();
 }
 
@@ -130,11 +132,16 @@ __device__ __forceinline__ void materialize(cpx<T>* r) {
 // spectrum (last-stage positions) out.
 template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
 __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
-                                            T* lds) {
+                                            T* lds, bool act = true) {
+  cpx<T> w[F::NS > 1 ? F::NS - 1 : 1] = {};  // every stage's root, loaded up front
+  static_for<F::NS - 1>([&](auto tt) {
+    constexpr int t = decltype(tt)::value;
+    w[t] = F::template dif_root<T, t>(tau, tw);
+  });
   static_for<F::NS>([&](auto tt) {
     constexpr int t = decltype(tt)::value;
-    F::template dif_stage<T, t>(reg, tau, tw);
-    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST, TW>(reg, tau, lds);
+    if (act) F::template dif_stage_w<T, t>(reg, w[t < F::NS - 1 ? t : 0]);
+    if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST, TW>(reg, tau, lds, act);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }
@@ -142,11 +149,16 @@ __device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* 
 // Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order out.
 template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
 __device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
-                                            T* lds) {
+                                            T* lds, bool act = true) {
+  cpx<T> w[F::NS > 1 ? F::NS - 1 : 1] = {};  // every stage's root, loaded up front
+  static_for<F::NS - 1>([&](auto tt) {
+    constexpr int t = decltype(tt)::value;
+    w[t] = F::template dit_root<T, t>(tau, tw);
+  });
   static_for<F::NS>([&](auto tt) {
     constexpr int t = F::NS - 1 - decltype(tt)::value;
-    F::template dit_stage<T, t>(reg, tau, tw);
-    if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST, TW>(reg, tau, lds);
+    if (act) F::template dit_stage_w<T, t>(reg, w[t < F::NS - 1 ? t : 0]);
+    if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST, TW>(reg, tau, lds, act);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }

@@ -270,39 +270,54 @@ struct Fft {
     return (beta / s) * blocklen(t) + (beta % s) + m * s;
   }
 
+  // Twiddle root of stage t for thread tau: stages before the last have radix
+  // PP, one butterfly per thread and one root (exp(-2 pi i k / L_t) forward;
+  // the inverse indexes the mirrored entry instead of conjugating, which keeps
+  // the compiler from holding the forward roots in registers until the
+  // inverse sweep).  The sweeps load every root up front, so the loads'
+  // latency overlaps the first stage instead of following each exchange.
   template <typename T, int t>
-  static RS_HD void dif_stage(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw) {
-    constexpr int R = radix(t);
-    constexpr int G = PP / R;
-    constexpr int s = stride(t);
+  static RS_HD cpx<T> dif_root(int tau, const cpx<T>* __restrict__ tw) {
+    static_assert(t < NS - 1, "the last stage has no twiddles");
     constexpr int twsh = LOGL - ilog2(blocklen(t));
-    static_for<G>([&](auto uu) {
+    return tw[(tau % stride(t)) << twsh];
+  }
+  template <typename T, int t>
+  static RS_HD cpx<T> dit_root(int tau, const cpx<T>* __restrict__ tw) {
+    static_assert(t < NS - 1, "the last stage has no twiddles");
+    constexpr int twsh = LOGL - ilog2(blocklen(t));
+    return tw[(L - ((tau % stride(t)) << twsh)) & (L - 1)];
+  }
+
+  // Stage t with its root w (ignored for the last stage).
+  template <typename T, int t>
+  static RS_HD void dif_stage_w(cpx<T>* reg, cpx<T> w) {
+    constexpr int R = radix(t);
+    static_for<PP / R>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
       Dft<T, R, -1>::run(reg + u * R);
-      if constexpr (t < NS - 1) {
-        const int k = (tau + u * TPF) % s;
-        apply_twiddles<T, R>(reg + u * R, tw[k << twsh]);
-      }
+      if constexpr (t < NS - 1) apply_twiddles<T, R>(reg + u * R, w);
+    });
+  }
+  template <typename T, int t>
+  static RS_HD void dit_stage_w(cpx<T>* reg, cpx<T> w) {
+    constexpr int R = radix(t);
+    static_for<PP / R>([&](auto uu) {
+      constexpr int u = decltype(uu)::value;
+      if constexpr (t < NS - 1) apply_twiddles<T, R>(reg + u * R, w);
+      Dft<T, R, +1>::run(reg + u * R);
     });
   }
 
   template <typename T, int t>
+  static RS_HD void dif_stage(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw) {
+    if constexpr (t < NS - 1) dif_stage_w<T, t>(reg, dif_root<T, t>(tau, tw));
+    else dif_stage_w<T, t>(reg, cpx<T>{(T)1, (T)0});
+  }
+  template <typename T, int t>
   static RS_HD void dit_stage(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw) {
-    constexpr int R = radix(t);
-    constexpr int G = PP / R;
-    constexpr int s = stride(t);
-    constexpr int twsh = LOGL - ilog2(blocklen(t));
-    static_for<G>([&](auto uu) {
-      constexpr int u = decltype(uu)::value;
-      if constexpr (t < NS - 1) {
-        const int k = (tau + u * TPF) % s;
-        // exp(+2 pi i k / L_t) = tw[L - (k << twsh)]: indexing the mirrored entry
-        // (instead of conjugating tw[k]) keeps the compiler from holding the
-        // forward twiddles in registers until the inverse sweep.
-        apply_twiddles<T, R>(reg + u * R, tw[(L - (k << twsh)) & (L - 1)]);
-      }
-      Dft<T, R, +1>::run(reg + u * R);
-    });
+    if constexpr (t < NS - 1) dit_stage_w<T, t>(reg, dit_root<T, t>(tau, tw));
+    else dit_stage_w<T, t>(reg, cpx<T>{(T)1, (T)0});
   }
 };
 

@@ -93,6 +93,17 @@ hipError_t launch_mv_cols(int L, const void* z, const double* t, double* out,
                           const Members& mb = Members::one(), const double* mk = nullptr,
                           bool z32 = false);
 
+// Tables of the symmetric sine transform along one direction (sd_kernels.hpp;
+// used by the tiled passes when L >= kSdMinL and twS is given): twS, the
+// twiddles exp(-2 pi i j / (L/16)) in the pass's precision; msl (x only), the
+// mirror slots of the upper halves of blocks 0 and 8 (2 L/16 entries, -1 at
+// frequency L/2).  With the symmetric form the x slots follow Sd<L>::slot and
+// pass B's y eigenvalues are indexed by block position (9 L/16 entries).
+struct SdTabs {
+  const void* twS = nullptr;
+  const int32_t* msl = nullptr;
+};
+
 // Sine-transform preconditioner, three passes; T = float or double internally.
 // tiled = false: Q, P1, P2 are [n2][n1+1] arrays.  tiled = true: Q is
 // strip-tiled (tile_index; 8 ceil((n1+1)/4) ceil(n2/2) T values) and the
@@ -103,7 +114,7 @@ hipError_t launch_mv_cols(int L, const void* z, const double* t, double* out,
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q,
                               const void* tw, int n1, int n2, bool tiled, hipStream_t s,
-                              const Members& mb = Members::one());
+                              const Members& mb = Members::one(), const SdTabs& sd = SdTabs{});
 // Pass B: column sine transforms of Q, the two eigenvalue scalings, two inverse
 // column transforms -> P1, P2 (slot layout in x, natural rows in y).
 // Batched: Q, P1, P2 advance by the member offset; with mk given, the
@@ -113,7 +124,7 @@ hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2,
                           double kx, double ky, double dpen, double Kfac, bool tiled,
                           hipStream_t s, const Members& mb = Members::one(),
-                          const double* mk = nullptr);
+                          const double* mk = nullptr, const SdTabs& sd = SdTabs{});
 // Raw sine transform (DST-I without normalisation) along the columns of
 // `batch` slices of [rows][ld] values (slice b at offset b * bstride):
 //   outA[k-1][ca] = sum_{p=1..rows} inA[p-1][ca] sin(pi k p / (rows + 1)), k = 1..rows,
@@ -129,7 +140,7 @@ template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw,
                               int n1, int n2, bool tiled, hipStream_t s,
-                              const Members& mb = Members::one());
+                              const Members& mb = Members::one(), const SdTabs& sd = SdTabs{});
 
 // Pass C fused with the matrix-vector row pass (n1 + 1 a power of two, so
 // L = 2(n1+1) is also the convolution length): z = pass C output (stored),
@@ -144,7 +155,8 @@ hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
                                  hipStream_t s, const Members& mb = Members::one(),
-                                 const double* mk = nullptr, bool z32 = false);
+                                 const double* mk = nullptr, bool z32 = false,
+                                 const SdTabs& sd = SdTabs{});
 
 // Chirp (Bluestein) form of the same preconditioner for any n (n + 1 not a
 // power of two): T internals, tables chn (n entries) and khat (L entries, in

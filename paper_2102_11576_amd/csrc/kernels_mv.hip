@@ -19,6 +19,13 @@ namespace rsfde {
 template <int L>
 struct MvCfg {
   using F = Fft<L, fft_pts(L)>;
+  // Register e of the first (and, inverse, last) stage sits at a position at or
+  // above L/2 >= n for every thread: zero on input, unused on output.
+  static constexpr bool upper(int e) {
+    for (int tau = 0; tau < F::TPF; ++tau)
+      if (F::pos(0, tau, e) < L / 2) return false;
+    return true;
+  }
   static constexpr int TPF = F::TPF;
   static constexpr int BR = (256 / TPF) > 0 ? (256 / TPF) : 1;             // FFTs per row block
   static constexpr int BC = (512 / TPF) > 16 ? 16 : ((512 / TPF) > 0 ? (512 / TPF) : 1);
@@ -51,15 +58,18 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu
   const int pair = blockIdx.x * C::BR + b;
   const int ra = 2 * pair, rb = 2 * pair + 1;
   const bool va = ra < n2, vb = rb < n2;
-  const double* za = z + (size_t)ra * n1;
-  const double* zb = z + (size_t)rb * n1;
+  const size_t ia0 = (size_t)(va ? ra : 0) * n1, ib0 = (size_t)(vb ? rb : 0) * n1;
   cpx<double> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
-    const int p = F::pos(0, tau, e);
-    const bool in = p < n1;
-    reg[e].re = (va && in) ? za[p] : 0.0;
-    reg[e].im = (vb && in) ? zb[p] : 0.0;
+    if constexpr (C::upper(e)) {
+      reg[e] = {0.0, 0.0};
+    } else {
+      const int p = F::pos(0, tau, e);
+      const bool in = p < n1;
+      reg[e].re = (va && in) ? z[ia0 + p] : 0.0;
+      reg[e].im = (vb && in) ? z[ib0 + p] : 0.0;
+    }
   });
   double* my = lds + b * lds_len(L);
   fft_forward<double, F>(reg, tau, tw, my);
@@ -71,24 +81,49 @@ __global__ __launch_bounds__(MvCfg<L>::THR_R) __attribute__((amdgpu_waves_per_eu
   });
   fft_inverse<double, F>(reg, tau, tw, my);
   const int hp = (n2 + 1) >> 1;
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    const int p = F::pos(0, tau, e);
-    if (p < n1) {
-      if (va) {
-        const size_t i = (size_t)ra * n1 + p;
-        double v = reg[e].re;
-        if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
-        if (sub) v -= theta * sub[i];
-        out[TO ? tile_index(ra, p, hp) : i] = v;
-      }
-      if (vb) {
-        const size_t i = (size_t)rb * n1 + p;
-        double v = reg[e].im;
-        if (mode == 0) v += (1.0 + dpen * (double)(1 - mask[i])) * z[i];
-        if (sub) v -= theta * sub[i];
-        out[TO ? tile_index(rb, p, hp) : i] = v;
-      }
+  // epilogue in groups of G registers: the group's loads (clamped addresses)
+  // all in flight at once, then its stores
+  constexpr int G = F::PP >= 2 ? 2 : F::PP;
+  static_for<F::PP / G>([&](auto gg) {
+    constexpr int g0 = decltype(gg)::value * G;
+    if constexpr (!C::upper(g0) || !C::upper(g0 + G - 1)) {
+      double za[G], zb[G], sa[G], sb[G];
+      uint8_t ma[G], mb2[G];
+      static_for<G>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const int p = F::pos(0, tau, g0 + k);
+        const int pp = p < n1 ? p : 0;
+        za[k] = zb[k] = sa[k] = sb[k] = 0.0;
+        ma[k] = mb2[k] = 1;
+        if (mode == 0) {
+          ma[k] = mask[ia0 + pp];
+          mb2[k] = mask[ib0 + pp];
+          za[k] = z[ia0 + pp];
+          zb[k] = z[ib0 + pp];
+        }
+        if (sub) {
+          sa[k] = sub[ia0 + pp];
+          sb[k] = sub[ib0 + pp];
+        }
+      });
+      static_for<G>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const int p = F::pos(0, tau, g0 + k);
+        if (p < n1) {
+          if (va) {
+            double v = reg[g0 + k].re;
+            if (mode == 0) v += (1.0 + dpen * (double)(1 - ma[k])) * za[k];
+            if (sub) v -= theta * sa[k];
+            out[TO ? tile_index(ra, p, hp) : (size_t)ra * n1 + p] = v;
+          }
+          if (vb) {
+            double v = reg[g0 + k].im;
+            if (mode == 0) v += (1.0 + dpen * (double)(1 - mb2[k])) * zb[k];
+            if (sub) v -= theta * sb[k];
+            out[TO ? tile_index(rb, p, hp) : (size_t)rb * n1 + p] = v;
+          }
+        }
+      });
     }
   });
 }
@@ -125,13 +160,22 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
   const int ca = 2 * cp, cb = 2 * cp + 1;
   const bool va = ca < n1, vb = cb < n1;
   cpx<double> reg[F::PP];
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    const int p = F::pos(0, tau, e);
-    const bool in = p < n2;
-    reg[e].re = (va && in) ? (double)z[(size_t)p * n1 + ca] : 0.0;
-    reg[e].im = (vb && in) ? (double)z[(size_t)p * n1 + cb] : 0.0;
-  });
+  {  // loads from clamped addresses, all in flight at once
+    const int cca = va ? ca : 0, ccb = vb ? cb : 0;
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      if constexpr (C::upper(e)) {
+        reg[e] = {0.0, 0.0};
+      } else {
+        const int p = F::pos(0, tau, e);
+        const bool in = p < n2;
+        const size_t rp = (size_t)(in ? p : 0) * n1;
+        const double a = (double)z[rp + cca], bb = (double)z[rp + ccb];
+        reg[e].re = (va && in) ? a : 0.0;
+        reg[e].im = (vb && in) ? bb : 0.0;
+      }
+    });
+  }
   double* my = lds + b;  // regions interleaved (stride BC)
   fft_forward<double, F, true, C::BC>(reg, tau, tw, my);
   static_for<F::PP>([&](auto ee) {
@@ -142,28 +186,49 @@ __global__ __launch_bounds__(MvCfg<L>::THR_C) __attribute__((amdgpu_waves_per_eu
   });
   fft_inverse<double, F, true, C::BC>(reg, tau, tw, my);
   const int hp = (n2 + 1) >> 1;
-  static_for<F::PP>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    const int p = F::pos(0, tau, e);
-    if (p < n2) {
-      const size_t i = (size_t)p * n1 + ca;
-      double ta = 0.0, tb = 0.0;
-      if constexpr (MODE == 0) {
-        if constexpr (TT) {
+  const int cca = va ? ca : 0;
+  if constexpr (MODE == 0 && TT) {
+    // epilogue in groups of 4 registers: the group's loads of t (clamped
+    // addresses) all in flight at once, then its stores
+    constexpr int G = F::PP >= 4 ? 4 : F::PP;
+    static_for<F::PP / G>([&](auto gg) {
+      constexpr int g0 = decltype(gg)::value * G;
+      if constexpr (!C::upper(g0) || !C::upper(g0 + G - 1)) {
+        double2 q[G];
+        static_for<G>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          const int p = F::pos(0, tau, g0 + k);
           // ca is even: (ca, cb) are adjacent in one tile row (cb = n1 is the
           // strip's padding column, read but not used)
-          const double2 q = va ? *(const double2*)(t + tile_index(p, ca, hp)) : double2{0.0, 0.0};
-          ta = q.x;
-          tb = q.y;
-        } else {
+          q[k] = *(const double2*)(t + tile_index(p < n2 ? p : 0, cca, hp));
+        });
+        static_for<G>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          const int p = F::pos(0, tau, g0 + k);
+          if (p < n2) {
+            const size_t i = (size_t)p * n1 + ca;
+            if (va) out[i] = reg[g0 + k].re + q[k].x;
+            if (vb) out[i + 1] = reg[g0 + k].im + q[k].y;
+          }
+        });
+      }
+    });
+  } else {
+    static_for<F::PP>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const int p = F::pos(0, tau, e);
+      if (p < n2) {
+        const size_t i = (size_t)p * n1 + ca;
+        double ta = 0.0, tb = 0.0;
+        if constexpr (MODE == 0) {
           ta = va ? t[i] : 0.0;
           tb = vb ? t[i + 1] : 0.0;
         }
+        if (va) out[i] = reg[e].re + ta;
+        if (vb) out[i + 1] = reg[e].im + tb;
       }
-      if (va) out[i] = reg[e].re + ta;
-      if (vb) out[i + 1] = reg[e].im + tb;
-    }
-  });
+    });
+  }
 }
 
 template <int L>

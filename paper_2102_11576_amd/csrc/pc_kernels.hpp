@@ -542,6 +542,12 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
   });
 }
 
+}  // namespace rsfde
+
+#include "sd_kernels.hpp"
+
+namespace rsfde {
+
 // ------------------------------- launchers --------------------------------
 template <typename T, int L, bool TL>
 static hipError_t pc_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* tw,
@@ -618,17 +624,134 @@ static hipError_t dst_cols_impl(const T* inA, const T* inB, T* outA, T* outB, co
   return hipGetLastError();
 }
 
+template <typename T, int L>
+static hipError_t sd_rows_fwd_impl(const double* v, const double* sig, T* Q, const void* twL,
+                                   const void* twS, int n1, int n2, hipStream_t s,
+                                   const Members& mb) {
+  using C = SdRows<L>;
+  const int pairs = (n2 + 1) / 2;
+  const int blocks = (pairs + C::ND - 1) / C::ND;
+  hipLaunchKernelGGL((k_sd_rows_fwd<T, L>), dim3(blocks, 1, mb.n), dim3(C::THR), 0, s, v, sig, Q,
+                     (const cpx<T>*)twL, (const cpx<T>*)twS, n1, n2, mb);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t sd_cols_impl(const T* Q, T* P, const T* lamx, const T* lamy, const void* twL,
+                               const void* twS, int n1, int n2, double kx, double ky,
+                               double dpen, double Kfac, hipStream_t s, const Members& mb,
+                               const double* mk) {
+  using C = SdCols<L>;
+  constexpr int BC = C::BC;
+  const int pairs = (n1 + 1) / 2;
+  const int blocks = (pairs + BC - 1) / BC;
+  hipLaunchKernelGGL((k_sd_cols<T, L>), dim3(blocks, 1, mb.n), dim3(C::THR), 0, s, Q, P, lamx,
+                     lamy, (const cpx<T>*)twL, (const cpx<T>*)twS, n1, n2, (T)kx, (T)ky, (T)dpen,
+                     (T)(0.5 * Kfac), mb, mk);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t sd_rows_inv_impl(const T* P, const uint8_t* mask, double* z, const void* twL,
+                                   const void* twS, const int32_t* msl, int n1, int n2,
+                                   hipStream_t s, const Members& mb) {
+  using C = SdRows<L>;
+  const int blocks = (n2 + C::ND - 1) / C::ND;
+  hipLaunchKernelGGL((k_sd_rows_inv<T, L>), dim3(blocks, 1, mb.n), dim3(C::THR), 0, s, P, mask, z,
+                     (const cpx<T>*)twL, (const cpx<T>*)twS, msl, n1, n2, mb);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t sd_rows_inv_mv_impl(const T* P, const uint8_t* mask, void* z, bool z32,
+                                      double* t, const void* twL, const void* twS,
+                                      const int32_t* msl, const void* tw64, const double* sym,
+                                      double coef, double dpen, const double* sub, double theta,
+                                      int n1, int n2, hipStream_t s, const Members& mb,
+                                      const double* mk) {
+  using M = SdMvCfg<L>;
+  const int blocks = (n2 + 1) / 2;
+  if (z32)
+    hipLaunchKernelGGL((k_sd_rows_inv_mv<T, L, float>), dim3(blocks, 1, mb.n), dim3(M::THR), 0, s,
+                       P, mask, (float*)z, t, (const cpx<T>*)twL, (const cpx<T>*)twS, msl,
+                       (const cpx<double>*)tw64, sym, coef, dpen, sub, theta, n1, n2, mb, mk);
+  else
+    hipLaunchKernelGGL((k_sd_rows_inv_mv<T, L>), dim3(blocks, 1, mb.n), dim3(M::THR), 0, s, P,
+                       mask, (double*)z, t, (const cpx<T>*)twL, (const cpx<T>*)twS, msl,
+                       (const cpx<double>*)tw64, sym, coef, dpen, sub, theta, n1, n2, mb, mk);
+  return hipGetLastError();
+}
+
+// Pass selection: the symmetric form for the tiled layouts when its tables are
+// given and L >= kSdMinL, the plain FFT form otherwise.
+template <typename T, int L>
+static hipError_t rows_fwd_any(const double* v, const double* sig, T* Q, const void* tw, int n1,
+                               int n2, bool tiled, hipStream_t s, const Members& mb,
+                               const SdTabs& sd) {
+  if constexpr (L >= kSdMinL) {
+    if (tiled && sd.twS) return sd_rows_fwd_impl<T, L>(v, sig, Q, tw, sd.twS, n1, n2, s, mb);
+  }
+  return tiled ? pc_rows_fwd_impl<T, L, true>(v, sig, Q, tw, n1, n2, s, mb)
+               : pc_rows_fwd_impl<T, L, false>(v, sig, Q, tw, n1, n2, s, mb);
+}
+
+template <typename T, int L>
+static hipError_t cols_any(const T* Q, T* P1, T* P2, const T* lamx, const T* lamy, const void* tw,
+                           int n1, int n2, double kx, double ky, double dpen, double Kfac,
+                           bool tiled, hipStream_t s, const Members& mb, const double* mk,
+                           const SdTabs& sd) {
+  if constexpr (L >= kSdMinL) {
+    if (tiled && sd.twS)
+      return sd_cols_impl<T, L>(Q, P1, lamx, lamy, tw, sd.twS, n1, n2, kx, ky, dpen, Kfac, s, mb,
+                                mk);
+  }
+  return tiled ? pc_cols_impl<T, L, true>(Q, P1, P2, lamx, lamy, tw, n1, n2, kx, ky, dpen, Kfac,
+                                          s, mb, mk)
+               : pc_cols_impl<T, L, false>(Q, P1, P2, lamx, lamy, tw, n1, n2, kx, ky, dpen, Kfac,
+                                           s, mb, mk);
+}
+
+template <typename T, int L>
+static hipError_t rows_inv_any(const T* P1, const T* P2, const uint8_t* mask, double* z,
+                               const void* tw, int n1, int n2, bool tiled, hipStream_t s,
+                               const Members& mb, const SdTabs& sd) {
+  if constexpr (L >= kSdMinL) {
+    if (tiled && sd.twS)
+      return sd_rows_inv_impl<T, L>(P1, mask, z, tw, sd.twS, sd.msl, n1, n2, s, mb);
+  }
+  return tiled ? pc_rows_inv_impl<T, L, true>(P1, P2, mask, z, tw, n1, n2, s, mb)
+               : pc_rows_inv_impl<T, L, false>(P1, P2, mask, z, tw, n1, n2, s, mb);
+}
+
+template <typename T, int L>
+static hipError_t rows_inv_mv_any(const T* P1, const T* P2, const uint8_t* mask, void* z,
+                                  bool z32, double* t, const void* twT, const void* tw64,
+                                  const double* sym, double coef, double dpen, const double* sub,
+                                  double theta, int n1, int n2, bool tiled, hipStream_t s,
+                                  const Members& mb, const double* mk, const SdTabs& sd) {
+  if constexpr (L >= kSdMinL) {
+    if (tiled && sd.twS)
+      return sd_rows_inv_mv_impl<T, L>(P1, mask, z, z32, t, twT, sd.twS, sd.msl, tw64, sym, coef,
+                                       dpen, sub, theta, n1, n2, s, mb, mk);
+  }
+  return tiled ? pc_rows_inv_mv_impl<T, L, true>(P1, P2, mask, z, z32, t, twT, tw64, sym, coef,
+                                                 dpen, sub, theta, n1, n2, s, mb, mk)
+               : pc_rows_inv_mv_impl<T, L, false>(P1, P2, mask, z, z32, t, twT, tw64, sym, coef,
+                                                  dpen, sub, theta, n1, n2, s, mb, mk);
+}
+
 #define RSFDE_LD_CASES(X) \
   X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
 template <typename T>
 hipError_t launch_pc_rows_fwd(int Lx, const double* v, const double* sig, T* Q, const void* tw,
-                              int n1, int n2, bool tiled, hipStream_t s, const Members& mb) {
+                              int n1, int n2, bool tiled, hipStream_t s, const Members& mb,
+                              const SdTabs& sd) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   switch (Lx) {
-#define X(LL)                                                               \
-  case LL:                                                                  \
-    return tiled ? pc_rows_fwd_impl<T, LL, true>(v, sig, Q, tw, n1, n2, s, mb) \
-                 : pc_rows_fwd_impl<T, LL, false>(v, sig, Q, tw, n1, n2, s, mb);
+#define X(LL) \
+  case LL:    \
+    return rows_fwd_any<T, LL>(v, sig, Q, tw, n1, n2, tiled, s, mb, sd);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -640,14 +763,13 @@ template <typename T>
 hipError_t launch_pc_cols(int Ly, const T* Q, T* P1, T* P2, const T* lamx_slot,
                           const T* lamy_pos, const void* tw, int n1, int n2, double kx, double ky,
                           double dpen, double Kfac, bool tiled, hipStream_t s, const Members& mb,
-                          const double* mk) {
+                          const double* mk, const SdTabs& sd) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   switch (Ly) {
-#define X(LL)                                                                                   \
-  case LL:                                                                                      \
-    return tiled ? pc_cols_impl<T, LL, true>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, \
-                                             dpen, Kfac, s, mb, mk)                             \
-                 : pc_cols_impl<T, LL, false>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx,   \
-                                              ky, dpen, Kfac, s, mb, mk);
+#define X(LL)                                                                                 \
+  case LL:                                                                                    \
+    return cols_any<T, LL>(Q, P1, P2, lamx_slot, lamy_pos, tw, n1, n2, kx, ky, dpen, Kfac, tiled, \
+                           s, mb, mk, sd);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -674,12 +796,12 @@ hipError_t launch_dst_cols(int L, const T* inA, const T* inB, T* outA, T* outB, 
 template <typename T>
 hipError_t launch_pc_rows_inv(int Lx, const T* P1, const T* P2,
                               const uint8_t* mask, double* z, const void* tw, int n1, int n2,
-                              bool tiled, hipStream_t s, const Members& mb) {
+                              bool tiled, hipStream_t s, const Members& mb, const SdTabs& sd) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   switch (Lx) {
-#define X(LL)                                                                      \
-  case LL:                                                                         \
-    return tiled ? pc_rows_inv_impl<T, LL, true>(P1, P2, mask, z, tw, n1, n2, s, mb) \
-                 : pc_rows_inv_impl<T, LL, false>(P1, P2, mask, z, tw, n1, n2, s, mb);
+#define X(LL) \
+  case LL:    \
+    return rows_inv_any<T, LL>(P1, P2, mask, z, tw, n1, n2, tiled, s, mb, sd);
     RSFDE_LD_CASES(X)
 #undef X
     default:
@@ -692,14 +814,14 @@ hipError_t launch_pc_rows_inv_mv(int L, const T* P1, const T* P2,
                                  const uint8_t* mask, void* z, double* t, const void* twT,
                                  const void* tw64, const double* sym, double coef, double dpen,
                                  const double* sub, double theta, int n1, int n2, bool tiled,
-                                 hipStream_t s, const Members& mb, const double* mk, bool z32) {
+                                 hipStream_t s, const Members& mb, const double* mk, bool z32,
+                                 const SdTabs& sd) {
+  if (mb.n < 1 || mb.n > kMaxBatch) return hipErrorInvalidValue;
   switch (L) {
-#define X(LL)                                                                                    \
-  case LL:                                                                                       \
-    return tiled ? pc_rows_inv_mv_impl<T, LL, true>(P1, P2, mask, z, z32, t, twT, tw64, sym,     \
-                                                    coef, dpen, sub, theta, n1, n2, s, mb, mk)   \
-                 : pc_rows_inv_mv_impl<T, LL, false>(P1, P2, mask, z, z32, t, twT, tw64, sym,    \
-                                                     coef, dpen, sub, theta, n1, n2, s, mb, mk);
+#define X(LL)                                                                                  \
+  case LL:                                                                                     \
+    return rows_inv_mv_any<T, LL>(P1, P2, mask, z, z32, t, twT, tw64, sym, coef, dpen, sub,    \
+                                  theta, n1, n2, tiled, s, mb, mk, sd);
     RSFDE_LD_CASES(X)
 #undef X
     default:

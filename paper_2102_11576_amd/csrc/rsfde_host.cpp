@@ -22,6 +22,7 @@
 #include "../../include/rsfde.h"
 #include "internal.hpp"
 #include "tables.hpp"
+#include "sd_engine.hpp"
 
 namespace rsfde {
 
@@ -92,6 +93,10 @@ struct Plan {
   double* lamy64 = nullptr;
   float* lamx32 = nullptr;
   float* lamy32 = nullptr;
+  // symmetric sine transform (two-dimensional passes, L >= kSdMinL): used along
+  // x / y, and the mirror slots of the x transform
+  bool sdx = false, sdy = false;
+  int32_t* msl = nullptr;
   // chirp-form preconditioner (n + 1 not a power of two)
   double* lamx_n = nullptr;  // tau eigenvalues, natural order, unit k
   double* lamy_n = nullptr;
@@ -452,6 +457,24 @@ int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<in
   return matvec_cols3(P, z, w, s);
 }
 
+// Symmetric-transform tables of the x (rows) and y (columns) passes in the
+// precision of T (empty where the plain FFT form is used).
+template <typename T>
+SdTabs sd_x(Plan* P) {
+  SdTabs t;
+  if (P->sdx) {
+    t.twS = (sizeof(T) == 8 ? P->tw64 : P->tw32)[P->Ldx / 16];
+    t.msl = P->msl;
+  }
+  return t;
+}
+template <typename T>
+SdTabs sd_y(Plan* P) {
+  SdTabs t;
+  if (P->sdy) t.twS = (sizeof(T) == 8 ? P->tw64 : P->tw32)[P->Ldy / 16];
+  return t;
+}
+
 int precond_impl(Plan* P, const double* r, const double* sig, double* z, int precision,
                  hipStream_t s) {
   if (P->is3d) {
@@ -479,17 +502,19 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
-      CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s));
+      CK(launch_pc_rows_fwd<double>(P->Ldx, r, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s,
+                                    Members::one(), sd_x<double>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 24.0 * S);
       CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
-                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s, Members::one(),
+                                nullptr, sd_y<double>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 16.0 * S + 9.0 * N);
       CK(launch_pc_rows_inv<double>(P->Ldx, P1, P2, P->mask, z, P->tw64[P->Ldx],
-                                    P->n1, P->n2, true, s));
+                                    P->n1, P->n2, true, s, Members::one(), sd_x<double>(P)));
     }
     return RSFDE_OK;
   }
@@ -497,17 +522,19 @@ int precond_impl(Plan* P, const double* r, const double* sig, double* z, int pre
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
-      CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s));
+      CK(launch_pc_rows_fwd<float>(P->Ldx, r, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s,
+                                   Members::one(), sd_x<float>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 12.0 * S);
       CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
-                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s, Members::one(),
+                               nullptr, sd_y<float>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcRowsInv, 8.0 * S + 9.0 * N);
       CK(launch_pc_rows_inv<float>(P->Ldx, P1, P2, P->mask, z, P->tw32[P->Ldx],
-                                   P->n1, P->n2, true, s));
+                                   P->n1, P->n2, true, s, Members::one(), sd_x<float>(P)));
     }
     return RSFDE_OK;
   }
@@ -544,37 +571,41 @@ int precond_matvec_impl(Plan* P, const double* v, const double* sig, void* zv, d
     double *Q = (double*)P->Q, *P1 = (double*)P->P1, *P2 = (double*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 8.0 * S);
-      CK(launch_pc_rows_fwd<double>(P->Ldx, v, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s));
+      CK(launch_pc_rows_fwd<double>(P->Ldx, v, sig, Q, P->tw64[P->Ldx], P->n1, P->n2, true, s,
+                                    Members::one(), sd_x<double>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 24.0 * S);
       CK(launch_pc_cols<double>(P->Ldy, Q, P1, P2, P->lamx64, P->lamy64, P->tw64[P->Ldy], P->n1,
-                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
+                                P->n2, P->kx, P->ky, P->dpen, Kfac, true, s, Members::one(),
+                                nullptr, sd_y<double>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 16.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<double>(P->Ldx, P1, P2, P->mask, z, P->t,
                                        P->tw64[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
                                        sub, theta, P->n1, P->n2, true, s, Members::one(), nullptr,
-                                       z32));
+                                       z32, sd_x<double>(P)));
     }
   } else {
     float *Q = (float*)P->Q, *P1 = (float*)P->P1, *P2 = (float*)P->P2;
     {
       ProfScope ps(P, s, kCatPcRows, 8.0 * N + 4.0 * S);
-      CK(launch_pc_rows_fwd<float>(P->Ldx, v, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s));
+      CK(launch_pc_rows_fwd<float>(P->Ldx, v, sig, Q, P->tw32[P->Ldx], P->n1, P->n2, true, s,
+                                   Members::one(), sd_x<float>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcCols, 12.0 * S);
       CK(launch_pc_cols<float>(P->Ldy, Q, P1, P2, P->lamx32, P->lamy32, P->tw32[P->Ldy], P->n1,
-                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s));
+                               P->n2, P->kx, P->ky, P->dpen, Kfac, true, s, Members::one(),
+                               nullptr, sd_y<float>(P)));
     }
     {
       ProfScope ps(P, s, kCatPcInvMv, 8.0 * S + 17.0 * N + extra);
       CK(launch_pc_rows_inv_mv<float>(P->Ldx, P1, P2, P->mask, z, P->t,
                                       P->tw32[P->Ldx], P->tw64[P->Ldx], P->symx, -P->kx, P->dpen,
                                       sub, theta, P->n1, P->n2, true, s, Members::one(), nullptr,
-                                      z32));
+                                      z32, sd_x<float>(P)));
     }
   }
   {
@@ -1215,6 +1246,62 @@ std::vector<double> pos_eigs(const std::vector<double>& ly, int L) {
   return lam;
 }
 
+// Tables of the symmetric sine transform of length L (sd_engine.hpp) for the
+// eigenvalues lam (natural order, lam[k-1] at DST index k): in slot order
+// (x direction), in block-position order (y direction, 9 L/16 entries), and
+// the mirror slots of the upper halves of blocks 0 and 8 (-1 at frequency L/2).
+template <int L>
+void sd_tables_L(const std::vector<double>& lam, std::vector<double>* by_slot,
+                 std::vector<double>* by_pos, std::vector<int32_t>* msl) {
+  using S = Sd<L>;
+  using Fs = typename S::Fs;
+  const int n = (int)lam.size();
+  auto lam_of = [&](int f) {
+    const int k = S::fold(f);
+    return (k >= 1 && k <= n) ? lam[k - 1] : 0.0;
+  };
+  std::vector<int> slot_at(S::NPOS, -1), slot_of_freq(L, -1);
+  for (int r = 0; r < 9; ++r)
+    for (int tau = 0; tau < S::TS; ++tau)
+      for (int e = 0; e < 16; ++e) {
+        const int P = r * S::LS + Fs::pos(Fs::NS - 1, tau, e);
+        const int c = S::slot(r, tau, e);
+        slot_at[P] = c;
+        if (c >= 0) slot_of_freq[S::freq(P)] = c;
+      }
+  if (by_slot) {
+    by_slot->assign(L / 2, 0.0);
+    for (int P = 0; P < S::NPOS; ++P)
+      if (slot_at[P] >= 0) (*by_slot)[slot_at[P]] = lam_of(S::freq(P));
+  }
+  if (by_pos) {
+    by_pos->assign(S::NPOS, 0.0);
+    for (int P = 0; P < S::NPOS; ++P) (*by_pos)[P] = lam_of(S::freq(P));
+  }
+  if (msl) {
+    msl->assign(2 * S::LS, -1);
+    for (int h = 0; h < 2; ++h)
+      for (int q = 0; q < S::LS; ++q) {
+        const int P = (h ? 8 : 0) * S::LS + q;
+        if (slot_at[P] >= 0) continue;
+        const int g = L - S::freq(P);
+        (*msl)[h * S::LS + q] = (g == L / 2) ? -1 : slot_of_freq[g];
+      }
+  }
+}
+
+bool sd_tables(int L, const std::vector<double>& lam, std::vector<double>* by_slot,
+               std::vector<double>* by_pos, std::vector<int32_t>* msl) {
+  switch (L) {
+    case 512: sd_tables_L<512>(lam, by_slot, by_pos, msl); return true;
+    case 1024: sd_tables_L<1024>(lam, by_slot, by_pos, msl); return true;
+    case 2048: sd_tables_L<2048>(lam, by_slot, by_pos, msl); return true;
+    case 4096: sd_tables_L<4096>(lam, by_slot, by_pos, msl); return true;
+    case 8192: sd_tables_L<8192>(lam, by_slot, by_pos, msl); return true;
+    default: return false;
+  }
+}
+
 }  // namespace
 }  // namespace rsfde
 
@@ -1328,8 +1415,23 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
 
   // Preconditioner tables (Section 4.1), in the layouts of the three passes.
   if (P->Ldx && P->Ldy) {
-    const std::vector<double> lamx = slot_eigs(tau_eigs(tx), P->Ldx);
-    const std::vector<double> lamy = pos_eigs(tau_eigs(ty), P->Ldy);
+    P->sdx = P->Ldx >= kSdMinL;
+    P->sdy = P->Ldy >= kSdMinL;
+    std::vector<double> lamx, lamy;
+    std::vector<int32_t> msl;
+    if (P->sdx) {
+      if (!sd_tables(P->Ldx, tau_eigs(tx), &lamx, nullptr, &msl)) return failx(__LINE__, RSFDE_EUNSUPPORTED);
+      if (upload(P, &P->msl, msl, s) != hipSuccess || ensure_twiddles(P, P->Ldx / 16, s) != hipSuccess)
+        return failx(__LINE__, RSFDE_ENOMEM);
+    } else {
+      lamx = slot_eigs(tau_eigs(tx), P->Ldx);
+    }
+    if (P->sdy) {
+      if (!sd_tables(P->Ldy, tau_eigs(ty), nullptr, &lamy, nullptr)) return failx(__LINE__, RSFDE_EUNSUPPORTED);
+      if (ensure_twiddles(P, P->Ldy / 16, s) != hipSuccess) return failx(__LINE__, RSFDE_ENOMEM);
+    } else {
+      lamy = pos_eigs(tau_eigs(ty), P->Ldy);
+    }
     std::vector<float> lamx_f(lamx.begin(), lamx.end()), lamy_f(lamy.begin(), lamy.end());
     if (upload(P, &P->lamx64, lamx, s) != hipSuccess || upload(P, &P->lamy64, lamy, s) != hipSuccess ||
         upload(P, &P->lamx32, lamx_f, s) != hipSuccess || upload(P, &P->lamy32, lamy_f, s) != hipSuccess)
@@ -1794,17 +1896,18 @@ int batch_precond(rsfde_batch_s* Bt, const double* v, const double* sig, double*
   const T* lamx = sizeof(T) == 8 ? (const T*)P->lamx64 : (const T*)P->lamx32;
   const T* lamy = sizeof(T) == 8 ? (const T*)P->lamy64 : (const T*)P->lamy32;
   const double Kfac = 4.0 / ((double)(P->n1 + 1) * (double)(P->n2 + 1));
-  CK(launch_pc_rows_fwd<T>(P->Ldx, v, sig, Q, tw[P->Ldx], P->n1, P->n2, true, s, mb));
+  CK(launch_pc_rows_fwd<T>(P->Ldx, v, sig, Q, tw[P->Ldx], P->n1, P->n2, true, s, mb, sd_x<T>(P)));
   CK(launch_pc_cols<T>(P->Ldy, Q, P1, nullptr, lamx, lamy, tw[P->Ldy], P->n1, P->n2, 0.0, 0.0,
-                       P->dpen, Kfac, true, s, mb, mk));
+                       P->dpen, Kfac, true, s, mb, mk, sd_y<T>(P)));
   if (!w) {
     CK(launch_pc_rows_inv<T>(P->Ldx, P1, nullptr, P->mask, z, tw[P->Ldx], P->n1, P->n2, true, s,
-                             mb));
+                             mb, sd_x<T>(P)));
     return RSFDE_OK;
   }
   double* t = Bt->region + Bt->o_t;
   CK(launch_pc_rows_inv_mv<T>(P->Ldx, P1, nullptr, P->mask, z, t, tw[P->Ldx], P->tw64[P->Ldx],
-                              P->symx, 0.0, P->dpen, nullptr, 0.0, P->n1, P->n2, true, s, mb, mk));
+                              P->symx, 0.0, P->dpen, nullptr, 0.0, P->n1, P->n2, true, s, mb, mk,
+                              false, sd_x<T>(P)));
   CK(launch_mv_cols(P->Lcy, z, t, w, P->symy, P->tw64[P->Lcy], P->n1, P->n2, 0.0, 0, s, 1, 0, true,
                     mb, mk + 1));
   return RSFDE_OK;

@@ -35,10 +35,10 @@ FAMILIES = [
     (r"k_update<", "update"),
     (r"k_mv_rows<", "mv_rows"),
     (r"k_mv_cols<", "mv_cols"),
-    (r"k_pc_rows_fwd<", "pc_rows_fwd"),
-    (r"k_pc_cols<", "pc_cols"),
-    (r"k_pc_rows_inv<", "pc_rows_inv"),
-    (r"k_pc_rows_inv_mv<", "pc_inv_mv_rows"),
+    (r"k_(pc|sd)_rows_fwd<", "pc_rows_fwd"),
+    (r"k_(pc|sd)_cols<", "pc_cols"),
+    (r"k_(pc|sd)_rows_inv<", "pc_rows_inv"),
+    (r"k_(pc|sd)_rows_inv_mv<", "pc_inv_mv_rows"),
     (r"k_dst_cols<", "dst_cols"),
     (r"k_gemm_bf16", "pc_gemm_bf16"),
     (r"k_residual\b", "residual"),
@@ -127,13 +127,13 @@ def _alg_bytes(name: str, n1: int, n2: int) -> float:
     if "k_mv_cols<" in name:
         return 24.0 * N
     ts = 8.0 if "<double" in name else 4.0
-    if "k_pc_rows_fwd<" in name:
+    if re.search(r"k_(pc|sd)_rows_fwd<", name):
         return 8.0 * N + ts * S
-    if "k_pc_cols<" in name:
+    if re.search(r"k_(pc|sd)_cols<", name):
         return 3.0 * ts * S
-    if "k_pc_rows_inv<" in name:
+    if re.search(r"k_(pc|sd)_rows_inv<", name):
         return 2.0 * ts * S + 9.0 * N
-    if "k_pc_rows_inv_mv<" in name:  # with the s-step shift term read (sub)
+    if re.search(r"k_(pc|sd)_rows_inv_mv<", name):  # with the s-step shift term read (sub)
         return 2.0 * ts * S + 25.0 * N
     return 0.0
 

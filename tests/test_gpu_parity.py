@@ -63,8 +63,11 @@ def test_matvec_parity(n1, n2):
     assert err <= 1e-13 * _norm_M_inf(p) * np.abs(Z).max(), err
 
 
+# From n + 1 = 256 on, a direction's sine transforms take the symmetric form
+# (half the FFT work); mixed shapes pair it with the plain form in the other
+# direction, odd n2 leaves a half-empty last row pair.
 PC_SHAPES = [(1, 1), (3, 3), (1, 7), (7, 3), (15, 15), (31, 63), (63, 63), (127, 127),
-             (255, 255), (511, 255)]
+             (255, 255), (511, 255), (255, 63), (63, 255), (1023, 15), (15, 1023)]
 
 
 @pytest.mark.parametrize("n1,n2", PC_SHAPES)
@@ -84,7 +87,7 @@ def test_precond_parity(n1, n2, precision, tol):
 # runs the preconditioner's last pass fused with the matvec row pass, with the
 # strip-tiled intermediates over n1 columns (partial strips included) and an
 # odd number of rows (a half-empty last row pair).
-RECT = [(3, 1), (1, 3), (7, 3), (3, 15), (15, 63), (63, 7), (127, 31)]
+RECT = [(3, 1), (1, 3), (7, 3), (3, 15), (15, 63), (63, 7), (127, 31), (255, 15), (15, 255)]
 
 
 @pytest.mark.parametrize("n1,n2", RECT)
