@@ -128,39 +128,65 @@ __device__ __forceinline__ void materialize(cpx<T>* r) {
   for (int e = 0; e < N; ++e) asm volatile("" : "+v"(r[e].re), "+v"(r[e].im));
 }
 
+// The twiddle roots of every stage of one sweep (one per stage but the last),
+// loaded up front so that their latency overlaps other work instead of
+// following each exchange.
+template <typename T, class F>
+struct Roots {
+  cpx<T> w[F::NS > 1 ? F::NS - 1 : 1] = {};
+  __device__ __forceinline__ void load_fwd(int tau, const cpx<T>* __restrict__ tw) {
+    static_for<F::NS - 1>([&](auto tt) {
+      constexpr int t = decltype(tt)::value;
+      w[t] = F::template dif_root<T, t>(tau, tw);
+    });
+  }
+  __device__ __forceinline__ void load_inv(int tau, const cpx<T>* __restrict__ tw) {
+    static_for<F::NS - 1>([&](auto tt) {
+      constexpr int t = decltype(tt)::value;
+      w[t] = F::template dit_root<T, t>(tau, tw);
+    });
+  }
+  __device__ __forceinline__ cpx<T> at(int t) const { return w[t < F::NS - 1 ? t : 0]; }
+};
+
 // Forward DIF sweep: natural order (stage-0 positions) in, digit-reversed
-// spectrum (last-stage positions) out.
+// spectrum (last-stage positions) out.  rt: the roots (Roots::load_fwd).
 template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
-__device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
-                                            T* lds, bool act = true) {
-  cpx<T> w[F::NS > 1 ? F::NS - 1 : 1] = {};  // every stage's root, loaded up front
-  static_for<F::NS - 1>([&](auto tt) {
-    constexpr int t = decltype(tt)::value;
-    w[t] = F::template dif_root<T, t>(tau, tw);
-  });
+__device__ __forceinline__ void fft_forward_r(cpx<T>* reg, int tau, const Roots<T, F>& rt,
+                                              T* lds, bool act = true) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = decltype(tt)::value;
-    if (act) F::template dif_stage_w<T, t>(reg, w[t < F::NS - 1 ? t : 0]);
+    if (act) F::template dif_stage_w<T, t>(reg, rt.at(t));
     if constexpr (t < F::NS - 1) lds_exchange<T, F, t, t + 1, ST, TW>(reg, tau, lds, act);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
 }
-
-// Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order out.
 template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
-__device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
+__device__ __forceinline__ void fft_forward(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
                                             T* lds, bool act = true) {
-  cpx<T> w[F::NS > 1 ? F::NS - 1 : 1] = {};  // every stage's root, loaded up front
-  static_for<F::NS - 1>([&](auto tt) {
-    constexpr int t = decltype(tt)::value;
-    w[t] = F::template dit_root<T, t>(tau, tw);
-  });
+  Roots<T, F> rt;
+  rt.load_fwd(tau, tw);
+  fft_forward_r<T, F, MAT, ST, TW>(reg, tau, rt, lds, act);
+}
+
+// Inverse DIT sweep: digit-reversed spectrum in, L * signal in natural order
+// out.  rt: the roots (Roots::load_inv).
+template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
+__device__ __forceinline__ void fft_inverse_r(cpx<T>* reg, int tau, const Roots<T, F>& rt,
+                                              T* lds, bool act = true) {
   static_for<F::NS>([&](auto tt) {
     constexpr int t = F::NS - 1 - decltype(tt)::value;
-    if (act) F::template dit_stage_w<T, t>(reg, w[t < F::NS - 1 ? t : 0]);
+    if (act) F::template dit_stage_w<T, t>(reg, rt.at(t));
     if constexpr (t > 0) lds_exchange<T, F, t, t - 1, ST, TW>(reg, tau, lds, act);
   });
   if constexpr (MAT) materialize<T, F::PP>(reg);
+}
+template <typename T, class F, bool MAT = true, int ST = 1, int TW = 64 / ST>
+__device__ __forceinline__ void fft_inverse(cpx<T>* reg, int tau, const cpx<T>* __restrict__ tw,
+                                            T* lds, bool act = true) {
+  Roots<T, F> rt;
+  rt.load_inv(tau, tw);
+  fft_inverse_r<T, F, MAT, ST, TW>(reg, tau, rt, lds, act);
 }
 
 // Strip-tiled layout of a [rows][cols] array of intermediates: tiles of

@@ -249,9 +249,12 @@ __global__ __launch_bounds__(PcColCfg<L>::THR_C) void k_pc_cols(
   });
   // Hide the table pointer from the optimiser so that the second sweep reloads
   // its twiddles instead of keeping the first sweep's in registers.
-  const cpx<T>* tw2 = tw;
-  const T* lamy2 = lamy_pos;
-  asm volatile("" : "+s"(tw2), "+s"(lamy2));
+  // (an opaque zero offset, not opaque pointers: those lose their global
+  // address space and their loads become flat loads)
+  int z0 = 0;
+  asm volatile("" : "+s"(z0));
+  const cpx<T>* tw2 = tw + z0;
+  const T* lamy2 = lamy_pos + z0;
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
     const T ly = ky * lamy2[F::pos(F::NS - 1, tau, e)];
@@ -471,14 +474,15 @@ void k_pc_rows_inv_mv(const T* __restrict__ P1, const T* __restrict__ P2,
   double zb[F::PP];  // row b's z at this thread's positions, kept for the convolution
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
-    // opaque copies: no per-point address is hoisted out of the loop
-    const T* P1h = P1;
-    const T* P2h = P2;
-    const cpx<T>* twh = twT;
-    ZT* zh = z;
-    const uint8_t* mh = mask;
-    int th = tau;
-    asm volatile("" : "+s"(P1h), "+s"(P2h), "+s"(twh), "+s"(zh), "+s"(mh), "+v"(th));
+    // opaque offsets: no per-point address is hoisted out of the loop (the
+    // pointers keep their global address space: opaque pointers would not)
+    int z0 = 0, th = tau;
+    asm volatile("" : "+s"(z0), "+v"(th));
+    const T* P1h = P1 + z0;
+    const T* P2h = P2 ? P2 + z0 : nullptr;
+    const cpx<T>* twh = twT + z0;
+    ZT* zh = z + z0;
+    const uint8_t* mh = mask + z0;
     const int r = ra + h;
     const bool vr = r < n2;
     T* myT = reinterpret_cast<T*>(my);

@@ -12,17 +12,18 @@
 
 namespace rsfde {
 
-// Transforms per block of the row passes and column pairs per block of pass B:
-// 32 / TS gives blocks of 288 threads (4.5 wavefronts, one transform = 9
-// sub-FFTs of TS threads each).
+// Transforms per block of the row passes and column pairs per block of pass B
+// (one transform = 9 sub-FFTs of TS threads each): one from L = 4096 on, 16 /
+// TS below.  Small blocks keep more of them resident per CU (pass B's pair
+// takes 38 KB of LDS with its stash), which hides more latency.
 template <int L>
 struct SdRows {
-  static constexpr int ND = 32 / Sd<L>::TS;
+  static constexpr int ND = Sd<L>::TS >= 16 ? 1 : 16 / Sd<L>::TS;
   static constexpr int THR = ND * Sd<L>::TPD;
 };
 template <int L>
 struct SdCols {
-  static constexpr int BC = 32 / Sd<L>::TS;
+  static constexpr int BC = Sd<L>::TS >= 16 ? 1 : 16 / Sd<L>::TS;
   static constexpr int THR = BC * Sd<L>::TPD;
 };
 // Threads of one sub-FFT inside one wavefront (ST: LDS interleave of the
@@ -34,15 +35,16 @@ constexpr int sd_tw() {
 }
 
 // Forward symmetric sweep of one transform.  Group-stage threads (g, group p)
-// hold the odd extension's values at positions p + LS m in v[] and the root
-// w1 = W_L^p (loaded with the values, so that its latency overlaps); after the
+// hold the odd extension's values at positions p + LS m in v[]; w1 = W_L^p and
+// rs, the sub-FFT roots, come loaded with the values (their latency overlaps
+// that of the data); after the
 // sweep, block-stage threads (block r, sub-FFT thread tau; all threads of the
 // transform) hold the spectrum of block r in v[] (sub-FFT DIF order).  The
 // group stage's 18 outputs go through the transform's LDS region one part at
 // a time (real, then imaginary), so v[] serves both roles.
 template <typename T, int L, int ST, int TWs, bool MAT>
 __device__ __forceinline__ void sd_forward(cpx<T>* v, bool g, int p, int r, int tau, cpx<T> w1,
-                                           const cpx<T>* __restrict__ twS, T* region,
+                                           const Roots<T, typename Sd<L>::Fs>& rs, T* region,
                                            bool act = true) {
   using S = Sd<L>;
   using Fs = typename S::Fs;
@@ -74,24 +76,23 @@ __device__ __forceinline__ void sd_forward(cpx<T>* v, bool g, int p, int r, int 
     if (act) lds_get<T, Fs, 0, ST>(v, tau, base, im);
     __syncthreads();
   }
-  fft_forward<T, Fs, MAT, ST, TWs>(v, tau, twS, base, act);
+  fft_forward_r<T, Fs, MAT, ST, TWs>(v, tau, rs, base, act);
 }
 
 // Inverse symmetric sweep: block-stage threads hold the odd spectrum of block
 // r in v[] (sub-FFT DIF order); afterwards group-stage threads (g, group q)
-// hold L times the odd extension at positions q + LS m in v[].
+// hold L times the odd extension at positions q + LS m in v[].  w1 = W_L^q and
+// rs (the sub-FFT roots, Roots::load_inv) are loaded by the caller up front.
 template <typename T, int L, int ST, int TWs, bool MAT>
-__device__ __forceinline__ void sd_inverse(cpx<T>* v, bool g, int q, int r, int tau,
-                                           const cpx<T>* __restrict__ twL,
-                                           const cpx<T>* __restrict__ twS, T* region,
+__device__ __forceinline__ void sd_inverse(cpx<T>* v, bool g, int q, int r, int tau, cpx<T> w1,
+                                           const Roots<T, typename Sd<L>::Fs>& rs, T* region,
                                            bool act = true) {
   using S = Sd<L>;
   using Fs = typename S::Fs;
   constexpr int LS = S::LS;
   constexpr int BL = LS + LS / 16;
   T* base = region + lds_pad(r * LS) * ST;
-  const cpx<T> w1 = twL[g ? q : 0];  // the group stage's root, loaded before the sub-FFTs
-  fft_inverse<T, Fs, MAT, ST, TWs>(v, tau, twS, base, act);
+  fft_inverse_r<T, Fs, MAT, ST, TWs>(v, tau, rs, base, act);
   const int qd = lds_pad(q), qm = lds_pad((LS - q) & (LS - 1));
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
@@ -219,6 +220,8 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_fwd(
   const double* xb = v + (size_t)(vb ? rb : 0) * n1;
   cpx<T> reg[16];
   const cpx<T> w1 = twL[g ? tg : 0];
+  Roots<T, typename S::Fs> rs;
+  rs.load_fwd(tau, twS);
   if (g) {
     static_for<16>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_fwd(
       reg[m].im = sb * b;
     });
   }
-  sd_forward<T, L, 1, sd_tw<L, 1>(), true>(reg, g, tg, r, tau, w1, twS, lds + d * S::LEN);
+  sd_forward<T, L, 1, sd_tw<L, 1>(), true>(reg, g, tg, r, tau, w1, rs, lds + d * S::LEN);
   if (!va) return;
   const T s = (T)(0.5 * (sig ? *sig : 1.0));
   const int hp = (n2 + 1) >> 1;
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_fwd(
 // per block, interleaved (column pair fastest in the thread index).
 // --------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(4))) void k_sd_cols(
+__global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(3))) void k_sd_cols(
     const T* __restrict__ Q, T* __restrict__ P, const T* __restrict__ lamx_slot,
     const T* __restrict__ lamy_blk, const cpx<T>* __restrict__ twL,
     const cpx<T>* __restrict__ twS, int n1, int n2, T kx, T ky, T dpen, T halfK,
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
   const int r = tg / S::TS, tau = tg % S::TS;
   cpx<T> reg[16];
   // the loads of the tables (clamped addresses) go out with the data's
-  const cpx<T> w1 = twL[g ? tg : 0];
+  const cpx<T> w1 = twL[g ? tg : 0];  // the group root of all three sweeps (W_L^p)
   const T lxa = kx * lamx_slot[va ? ca : 0], lxb = kx * lamx_slot[va ? cb : 0];
   if (g) {  // clamped loads, all in flight at once
     const int cc = va ? ca : 0;
@@ -302,24 +305,38 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
     });
   }
   T* my = lds + b;  // regions interleaved (stride BC)
-  sd_forward<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, twS, my);
+  {
+    Roots<T, Fs> rs;  // (loaded per sweep: held across the kernel they cost occupancy)
+    rs.load_fwd(tau, twS);
+    sd_forward<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, rs, my);
+  }
   // spectrum = 2 rho_b - 2i rho_a; rho_b waits in LDS for the second column
   // (in registers it would cost a wavefront of occupancy)
+  // The y eigenvalues stay in registers for the second column (a block of
+  // 2.25 wavefronts is held to 3 per SIMD by its LDS anyway).
   const T* lamy = lamy_blk + r * S::LS;
   T* rb = stash + tg * BC + b;
+  T ly[16];
   static_for<16>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
-    const T ly = ky * lamy[Fs::pos(Fs::NS - 1, tau, e)];
+    ly[e] = ky * lamy[Fs::pos(Fs::NS - 1, tau, e)];
+  });
+  static_for<16>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
     const T rho_a = (T)-0.5 * reg[e].im;
     rb[e * S::TPD * BC] = (T)0.5 * reg[e].re;
-    const T e1 = (T)1 - lxa - ly;
+    const T e1 = (T)1 - lxa - ly[e];
     const T e2 = e1 + dpen;
     const T q = halfK * rho_a / (e1 * e2);
     // (K rho / 2) (1/E2 - i/E1)
     reg[e].re = q * e1;
     reg[e].im = -q * e2;
   });
-  sd_inverse<T, L, BC, TWs, false>(reg, g, tg, r, tau, twL, twS, my);
+  {
+    Roots<T, Fs> rs;
+    rs.load_inv(tau, twS);
+    sd_inverse<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, rs, my);
+  }
   if (g && va) {
     static_for<16>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -330,23 +347,19 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
             neg ? V2{-reg[m].re, -reg[m].im} : V2{reg[m].re, reg[m].im};
     });
   }
-  // Hide the table pointers from the optimiser so that the second sweep reloads
-  // them instead of keeping the first sweep's values in registers.
-  const cpx<T>* twL2 = twL;
-  const cpx<T>* twS2 = twS;
-  const T* lamy2 = lamy;
-  asm volatile("" : "+s"(twL2), "+s"(twS2));
-  asm volatile("" : "+v"(lamy2));
   static_for<16>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
-    const T ly = ky * lamy2[Fs::pos(Fs::NS - 1, tau, e)];
-    const T e1 = (T)1 - lxb - ly;
+    const T e1 = (T)1 - lxb - ly[e];
     const T e2 = e1 + dpen;
     const T q = halfK * rb[e * S::TPD * BC] / (e1 * e2);
     reg[e].re = q * e1;
     reg[e].im = -q * e2;
   });
-  sd_inverse<T, L, BC, TWs, false>(reg, g, tg, r, tau, twL2, twS2, my);
+  {
+    Roots<T, Fs> rs;
+    rs.load_inv(tau, twS);
+    sd_inverse<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, rs, my);
+  }
   if (g && va) {
     static_for<16>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -383,8 +396,11 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_inv(
   const bool g = tg < S::NG;
   const int r = tg / S::TS, tau = tg % S::TS;
   cpx<T> reg[16];
+  const cpx<T> w1 = twL[g ? tg : 0];
+  Roots<T, typename S::Fs> rs;
+  rs.load_inv(tau, twS);
   sd_load_spectrum<T, L>(reg, P, row, vr, r, tau, n2, msl);
-  sd_inverse<T, L, 1, sd_tw<L, 1>(), true>(reg, g, tg, r, tau, twL, twS, lds + d * S::LEN);
+  sd_inverse<T, L, 1, sd_tw<L, 1>(), true>(reg, g, tg, r, tau, w1, rs, lds + d * S::LEN);
   if (g) sd_store_z<T, L, double>(reg, tg, row, vr, n1, mask, z, nullptr);
 }
 
@@ -454,19 +470,22 @@ void k_sd_rows_inv_mv(
     T* region = reinterpret_cast<T*>(lds + L / 2);
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      // opaque copies: nothing per point (slots, addresses) is hoisted out of
-      // the loop, where it would stay live across the whole transform
-      const T* Ph = P;
-      const int32_t* mh = msl;
+      // opaque copy of the thread index: nothing per point (slots, addresses) is
+      // hoisted out of the loop, where it would stay live across the whole
+      // transform (the pointers stay plain: an opaque pointer loses its global
+      // address space, and flat loads wait on LDS traffic too)
       int th = tid;
-      asm volatile("" : "+s"(Ph), "+s"(mh), "+v"(th));
+      asm volatile("" : "+v"(th));
       const bool g = th < S::NG;
       const int r = act ? th / S::TS : 0, tau = th % S::TS;
       const int row = ra + h;
       const bool vr = row < n2;
       cpx<T> reg[16];
-      if (act) sd_load_spectrum<T, L>(reg, Ph, row, vr, r, tau, n2, mh);
-      sd_inverse<T, L, 1, TWs, true>(reg, g, th, r, tau, twL, twS, region, act);
+      const cpx<T> w1 = twL[g ? th : 0];
+      Roots<T, typename S::Fs> rs;
+      rs.load_inv(tau, twS);
+      if (act) sd_load_spectrum<T, L>(reg, P, row, vr, r, tau, n2, msl);
+      sd_inverse<T, L, 1, TWs, true>(reg, g, th, r, tau, w1, rs, region, act);
       // (sd_inverse ends with a barrier: row b's staged z may replace the region)
       if (g) sd_store_z<T, L, ZT>(reg, th, row, vr, n1, mask, z, lds + h * (L / 2));
     }
@@ -475,6 +494,9 @@ void k_sd_rows_inv_mv(
   // ---- the convolution of z_a + i z_b
   const bool act = tid < F::TPF;
   const int tc = act ? tid : 0;
+  Roots<double, F> rcf, rci;  // both sweeps' roots, loaded up front
+  rcf.load_fwd(tc, tw64);
+  rci.load_inv(tc, tw64);
   cpx<double> reg[F::PP];
   static_for<F::PP>([&](auto ee) {
     constexpr int e = decltype(ee)::value;
@@ -488,7 +510,7 @@ void k_sd_rows_inv_mv(
     }
   });
   __syncthreads();  // the convolution's region overlays the staged z
-  fft_forward<double, F>(reg, tc, tw64, lds, act);
+  fft_forward_r<double, F>(reg, tc, rcf, lds, act);
   if (act) {
     static_for<F::PP>([&](auto ee) {
       constexpr int e = decltype(ee)::value;
@@ -497,7 +519,7 @@ void k_sd_rows_inv_mv(
       reg[e].im *= sc;
     });
   }
-  fft_inverse<double, F>(reg, tc, tw64, lds, act);
+  fft_inverse_r<double, F>(reg, tc, rci, lds, act);
   if (!act) return;
   // Epilogue in groups of G registers: the group's loads (clamped addresses)
   // all in flight at once, then its stores.
