@@ -34,6 +34,8 @@ template <int NT, int K>
 __device__ __forceinline__ void gram_chunks(size_t c0, size_t stride, int k4, const double* brow,
                                             bool bvalid, const double* const* arow,
                                             const bool* avalid, v4d* acc) {
+  // acc[0]: the U tile (U^T U), whose A operand is the B operand itself (the
+  // same row of U in the same lane), so U is read once; acc[1 + t]: Q tile t.
   double2 b[K][4], a[K][NT][4];
 #pragma unroll
   for (int u = 0; u < K; ++u) {
@@ -51,20 +53,24 @@ __device__ __forceinline__ void gram_chunks(size_t c0, size_t stride, int k4, co
 #pragma unroll
   for (int u = 0; u < K; ++u)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u][q].x, b[u][q].x, acc[0], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u][q].y, b[u][q].y, acc[0], 0, 0, 0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].x, b[u][q].x, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].y, b[u][q].y, acc[t], 0, 0, 0);
+        acc[1 + t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].x, b[u][q].x, acc[1 + t], 0, 0, 0);
+        acc[1 + t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t][q].y, b[u][q].y, acc[1 + t], 0, 0, 0);
       }
+    }
 }
 
-// U2 chunks per loop iteration (2 where the registers allow: NT <= 2).
+// NT Q tiles (m1 <= 16 NT) plus the U tile; U2 chunks per loop iteration (2
+// where the registers allow).
 template <int NT, int U2>
 __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict__ V, size_t ld,
                                                         int nr, int m1, int s, size_t N,
                                                         double* __restrict__ gpart) {
-  __shared__ double red[4][NT][64][4];
+  __shared__ double red[4][NT + 1][64][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
   const bool bvalid = i16 < s;
@@ -74,12 +80,12 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int r = 16 * t + i16;
-    avalid[t] = r < nr;
+    avalid[t] = r < m1;
     arow[t] = V + (size_t)(avalid[t] ? r : 0) * ld;
   }
-  v4d acc[NT];
+  v4d acc[NT + 1];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t <= NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
   // Chunks of 32 elements, wave by wave over the grid (gram_chunks).
   const size_t nchunks = N / 32;
@@ -95,27 +101,31 @@ __global__ __launch_bounds__(kGramThreads) void k_bgram(const double* __restrict
     for (int j = 0; j < 8; ++j) {
       const size_t e = e0 + j;
       const double bv = (bvalid && e < N) ? brow[e] : 0.0;
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, bv, acc[0], 0, 0, 0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const double av = (avalid[t] && e < N) ? arow[t][e] : 0.0;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        acc[1 + t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[1 + t], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t <= NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[wid][t][lane][q] = acc[t][q];
   __syncthreads();
   if (wid == 0) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t <= NT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double v = red[0][t][lane][q] + red[1][t][lane][q] + red[2][t][lane][q] +
                          red[3][t][lane][q];
-        const int r = 16 * t + k4 + 4 * q, c = i16;
-        if (r < nr && c < s) gpart[(size_t)(r * 16 + c) * kGramBlocks + blockIdx.x] = v;
+        const int rt = k4 + 4 * q, c = i16;  // row within the tile
+        // rows of G in [Q U] order: the U tile holds rows m1 + rt, Q tile t - 1 rows 16 (t - 1) + rt
+        const int r = t == 0 ? m1 + rt : 16 * (t - 1) + rt;
+        const bool ok = t == 0 ? rt < s : r < m1;
+        if (ok && c < s) gpart[(size_t)(r * 16 + c) * kGramBlocks + blockIdx.x] = v;
       }
   }
 }
@@ -227,18 +237,20 @@ __global__ __launch_bounds__(kRedThreads) void k_bupd(double* __restrict__ V, si
 hipError_t launch_bgram(const double* V, size_t ld, int nr, int m1, int s, size_t N,
                         double* gpart, double* G_host_dev, int32_t* seq_flag, int32_t seq,
                         int32_t* done_count, hipStream_t st) {
-  if (nr < 1 || s < 1 || s > 16 || nr > 16 * kGramMaxTiles) return hipErrorInvalidValue;
+  // rows: the m1 rows of Q followed by the s rows of U (nr = m1 + s)
+  if (nr < 1 || s < 1 || s > 16 || m1 < 1 || nr != m1 + s || nr > 16 * kGramMaxTiles)
+    return hipErrorInvalidValue;
   int nb = (int)((N / 32 + 4 * 4 - 1) / (4 * 4));  // >= 4 chunks per wave
   if (nb < 1) nb = 1;
   if (nb > kGramBlocks) nb = kGramBlocks;
-  const int nt = (nr + 15) / 16;
-  // Two tiles with two chunks per iteration run at occupancy 3: half the
-  // blocks measured faster there (2047^2: 203 -> 191 us at 31 rows).
-  if (nt == 2 && nb > kGramBlocks / 2) nb = kGramBlocks / 2;
+  const int nt = (m1 + 15) / 16;  // Q tiles; the U tile reuses the B operand's loads
+  // One Q tile (two tiles of MFMAs) with two chunks per iteration runs at
+  // occupancy 3: half the blocks measured faster there.
+  if (nt == 1 && nb > kGramBlocks / 2) nb = kGramBlocks / 2;
   const dim3 g(nb), b(kGramThreads);
   switch (nt) {
     case 1: hipLaunchKernelGGL((k_bgram<1, 2>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
-    case 2: hipLaunchKernelGGL((k_bgram<2, 2>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
+    case 2: hipLaunchKernelGGL((k_bgram<2, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
     case 3: hipLaunchKernelGGL((k_bgram<3, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
     case 4: hipLaunchKernelGGL((k_bgram<4, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
     case 5: hipLaunchKernelGGL((k_bgram<5, 1>), g, b, 0, st, V, ld, nr, m1, s, N, gpart); break;
