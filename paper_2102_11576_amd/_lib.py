@@ -4,6 +4,8 @@ Argument marshalling only: every step of the computation runs in the HIP
 library.  Functions keep the C names and take torch tensors (FP64 / uint8,
 contiguous, on the GPU) or raw device pointers.  Importing this module fails
 loudly if the library has not been built; there is no CPU fallback.
+RSFDE_LIBRARY names another build of the same library to load instead (the
+build whose host code carries the address and undefined-behaviour sanitizers).
 """
 
 from __future__ import annotations
@@ -12,7 +14,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librsfde.so")
+LIB_PATH = os.environ.get("RSFDE_LIBRARY") or os.path.join(_HERE, "librsfde.so")
 
 RSFDE_OK = 0
 RSFDE_EINVAL = -1

@@ -10,7 +10,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "rsfde.h")
-LIB = os.path.join(ROOT, "paper_2102_11576_amd", "librsfde.so")
+# RSFDE_LIBRARY: the host-sanitised build (tests/test_sanitize_cpu.py runs this
+# module's host checks against it)
+LIB = os.environ.get("RSFDE_LIBRARY") or os.path.join(ROOT, "paper_2102_11576_amd", "librsfde.so")
 
 
 def _declared():
