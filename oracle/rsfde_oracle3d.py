@@ -29,13 +29,14 @@ from typing import Tuple
 import numpy as np
 import scipy.linalg as sla
 
-from .rsfde_oracle import (G_dense, dst1_matrix, f_eval, gmres, riesz_c, tau_eigenvalues,
-                           tau_matrix, toeplitz_first_column)
+from .rsfde_oracle import (G_dense, dst1_matrix, f_eval, fprime_eval, gmres, riesz_c,
+                           tau_eigenvalues, tau_matrix, toeplitz_first_column)
 
 __all__ = [
     "Problem3", "problem3_from_workload", "A3_parts", "dense_A3", "dense_M3",
     "matvec3", "matvec3_fast", "matvec3_entry", "tau_eigs3", "precond3_apply",
     "precond3_apply_fft", "precond3_dense", "rhs3", "march3_lu", "march3_gmres",
+    "march3_lu_traj", "adjoint3_lu", "loss_and_grads3_lu",
 ]
 
 
@@ -238,3 +239,55 @@ def march3_gmres(p: Problem3, u0: np.ndarray, m: int, f_kind: int, restart: int,
         iters.append(it)
         u_prev2, u = u, x
     return u, iters
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the 3-D march (no counterpart in the paper): the two-dimensional
+# derivation with one more factor.  M is symmetric (each G^(alpha) is), so
+# with M u^k = u^{k-1} + dt mask f(u^{k-1}) and L = L(u^m):
+#   mu^k = M^{-1} lambda^k,  lambda^{k-1} = mu^k + dt mask f'(u^{k-1}) mu^k,
+#   dL/dk_s += mu^k . ((A_s / k_s along axis s) u^k)   (dM/dk_s = -A_s / k_s).
+# ---------------------------------------------------------------------------
+
+def march3_lu_traj(p: Problem3, u0: np.ndarray, m: int, f_kind: int):
+    """march3_lu keeping every state: [u^0, ..., u^m]."""
+    lu = sla.lu_factor(dense_M3(p))
+    traj = [u0.astype(np.float64).copy()]
+    for _ in range(m):
+        traj.append(sla.lu_solve(lu, rhs3(p, traj[-1], f_kind).ravel()).reshape(p.shape))
+    return traj
+
+
+def _unit_parts(p: Problem3):
+    """A_x / kx, A_y / ky, A_z / kz: the factors with unit k (defined at k = 0 too)."""
+    out = []
+    for axis, (alpha, n) in enumerate(((p.alpha1, p.n1), (p.alpha2, p.n2), (p.alpha3, p.n3))):
+        lo, hi = p.box[2 * axis], p.box[2 * axis + 1]
+        h = (hi - lo) / (n + 1)
+        out.append(p.dt * riesz_c(alpha) / h ** alpha * G_dense(alpha, n))
+    return out
+
+
+def adjoint3_lu(p: Problem3, traj, lam_m: np.ndarray, f_kind: int):
+    """Reverse sweep for L(u^m) given the forward trajectory [u^0..u^m].
+    Returns (lambda^0 = dL/du^0, dL/dkx, dL/dky, dL/dkz)."""
+    lu = sla.lu_factor(dense_M3(p))
+    Ux, Uy, Uz = _unit_parts(p)
+    lam = lam_m.astype(np.float64).copy()
+    g = [0.0, 0.0, 0.0]
+    for k in range(len(traj) - 1, 0, -1):
+        mu = sla.lu_solve(lu, lam.ravel()).reshape(p.shape)
+        uk = traj[k]
+        g[0] += float(np.sum(mu * _along(Ux, uk, 2)))
+        g[1] += float(np.sum(mu * _along(Uy, uk, 1)))
+        g[2] += float(np.sum(mu * _along(Uz, uk, 0)))
+        lam = mu + p.dt * p.mask * fprime_eval(f_kind, traj[k - 1]) * mu
+    return lam, g[0], g[1], g[2]
+
+
+def loss_and_grads3_lu(p: Problem3, u0: np.ndarray, m: int, f_kind: int, u_tgt: np.ndarray):
+    """L = ||u^m - u_tgt||^2 and its gradients w.r.t. (u0, kx, ky, kz)."""
+    traj = march3_lu_traj(p, u0, m, f_kind)
+    diff = traj[-1] - u_tgt
+    g0, gx, gy, gz = adjoint3_lu(p, traj, 2.0 * diff, f_kind)
+    return float(np.sum(diff * diff)), g0, gx, gy, gz

@@ -12,7 +12,10 @@ future work).  Each check ties it to something other than itself:
 * the preconditioner equals the dense formula with explicit inverses of the
   tau matrices, and inverts I - tau_1(A) exactly on an all-inside domain;
 * M is symmetric with spectrum >= 1 (the 3-D form of Lemma 2.3's argument);
-* GMRES on the axis-wise operators reaches the LU solution.
+* GMRES on the axis-wise operators reaches the LU solution;
+* the adjoint gradients (u0, kx, ky, kz) equal central finite differences of
+  the LU march, and with one z-slice its x and y gradients equal the
+  two-dimensional oracle's adjoint.
 """
 
 import numpy as np
@@ -132,3 +135,45 @@ def test_gmres3_matches_lu(side):
     u_g, iters = O.march3_gmres(p, w.u0, w.m, w.f_kind, 20, 1e-13, side=side)
     assert np.abs(u_g - u_lu).max() <= 1e-10 * np.abs(u_lu).max()
     assert all(i > 0 for i in iters)
+
+
+def _loss3(p, u0, m, f_kind, tgt):
+    u = O.march3_lu(p, u0, m, f_kind)
+    return float(np.sum((u - tgt) ** 2))
+
+
+@pytest.mark.parametrize("f_kind", [1, 3])
+def test_adjoint3_matches_central_fd(f_kind):
+    p = _p3((4, 5, 3))
+    rng = np.random.default_rng(11)
+    u0 = 0.3 * p.mask + 0.2 * rng.standard_normal(p.shape)
+    tgt = 0.1 * rng.standard_normal(p.shape)
+    m = 3
+    L, g0, gx, gy, gz = O.loss_and_grads3_lu(p, u0, m, f_kind, tgt)
+    assert L == pytest.approx(_loss3(p, u0, m, f_kind, tgt), rel=1e-14)
+    h = 1e-6
+    du = rng.standard_normal(p.shape)
+    import dataclasses
+    for d in ((1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1), (0.4, -0.6, 0.8, 1)):
+        pp = dataclasses.replace(p, kx=p.kx + h * d[0], ky=p.ky + h * d[1], kz=p.kz + h * d[2])
+        pm = dataclasses.replace(p, kx=p.kx - h * d[0], ky=p.ky - h * d[1], kz=p.kz - h * d[2])
+        fd = (_loss3(pp, u0 + h * d[3] * du, m, f_kind, tgt)
+              - _loss3(pm, u0 - h * d[3] * du, m, f_kind, tgt)) / (2 * h)
+        an = gx * d[0] + gy * d[1] + gz * d[2] + d[3] * float(np.sum(g0 * du))
+        assert an == pytest.approx(fd, rel=1e-6, abs=1e-9), d
+
+
+def test_adjoint3_one_slice_reduces_to_2d():
+    # one z-slice with kz = 0 is the two-dimensional problem
+    p = _p3((6, 5, 1), kz=0.0)
+    rng = np.random.default_rng(5)
+    u0 = 0.3 * p.mask + 0.2 * rng.standard_normal(p.shape)
+    tgt = 0.1 * rng.standard_normal(p.shape)
+    L, g0, gx, gy, _ = O.loss_and_grads3_lu(p, u0, 3, 1, tgt)
+    q = _slice2d(p, 0)
+    u, traj = O.march_lu(q, u0[0], 3, 1, keep_all=True)
+    g0_2, gx_2, gy_2 = O.adjoint_lu(q, traj, 2.0 * (u - tgt[0]), 1)
+    assert L == pytest.approx(float(np.sum((u - tgt[0]) ** 2)), rel=1e-12)
+    assert np.allclose(g0[0], g0_2, rtol=1e-11, atol=1e-14)
+    assert gx == pytest.approx(gx_2, rel=1e-11)
+    assert gy == pytest.approx(gy_2, rel=1e-11)
