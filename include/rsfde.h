@@ -151,8 +151,9 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
  * fastest), N = n1 n2 n3.  n1+1, n2+1 and n3+1 must be powers of two (each
  * n <= 4095; EUNSUPPORTED otherwise) and (n1+1) n2 n3 < 2^31.
  * rsfde_matvec, rsfde_precond_apply (FP64 / FP32), rsfde_step, rsfde_step_src,
- * rsfde_solve and rsfde_march_ensemble accept a 3-D plan; rsfde_set_coeffs,
- * rsfde_adjoint_step and the BF16 preconditioner return EUNSUPPORTED for it.
+ * rsfde_solve, rsfde_march_ensemble, rsfde_set_coeffs / rsfde_set_coeffs3 and
+ * rsfde_adjoint_step (three k gradients) accept a 3-D plan; the BF16
+ * preconditioner returns EUNSUPPORTED for it.
  * The plan owns four preconditioner intermediates of (n1+1) n2 n3 doubles and
  * one more vector than a 2-D plan.  Other arguments as rsfde_setup.
  * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED. */
@@ -167,9 +168,20 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
                  double alpha3, double kx, double ky, double kz, const uint8_t* mask_dev,
                  double eta, double dt, int32_t max_restart, void* stream);
 
-/* Change kx, ky (O(1): the symbols and eigenvalues are stored for k = 1 and
- * scaled at apply time).  Errors: EINVAL, EUNSUPPORTED (3-D plan). */
+/* Change kx, ky (Section 2's diffusion coefficients, constant here).  2-D
+ * plans: O(1), the symbols and eigenvalues are stored for k = 1 and scaled at
+ * apply time.  3-D plans: kz is kept; see rsfde_set_coeffs3.
+ * Errors: EINVAL (negative or non-finite k), EHIP. */
 int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky);
+
+/* Change kx, ky, kz of a 3-D plan.  kz is applied at launch; the
+ * preconditioner's folded x/y eigenvalue table carries kx and ky, so when they
+ * change it is rebuilt on the host and copied in after hipDeviceSynchronize
+ * (the call blocks; no work of the plan may be enqueued from another thread
+ * meanwhile).  A 2-D plan accepts kz = 0 only (as rsfde_set_coeffs).
+ * Errors: EINVAL (negative or non-finite k, kz != 0 on a 2-D plan), EHIP (the
+ * plan then keeps its previous kx, ky). */
+int rsfde_set_coeffs3(rsfde_plan plan, double kx, double ky, double kz);
 
 /* y = M x with M = I - A + D, A = I (x) A_x + A_y (x) I (matrix_vector,
  * toeplitz_A): two FFT-convolution passes.  x and y must not overlap.
@@ -244,9 +256,10 @@ int rsfde_solve(rsfde_plan plan, const double* b, double* x, const rsfde_solver_
  *   mu       = M^{-1} lam_cur                      (same preconditioned GMRES)
  *   dk[0]   += < mu, (I (x) A_x/kx) u_cur >         (dL/dkx contribution)
  *   dk[1]   += < mu, (A_y/ky (x) I) u_cur >         (dL/dky contribution)
+ *   dk[2]   += < mu, (A_z/kz (x) I (x) I) u_cur >   (3-D plans: dL/dkz)
  *   lam_prev = mu + dt * mask * f'(u_prev) * mu
  * u_prev = u^{k-1}, u_cur = u^k, lam_cur = dL/du^k; dk_dev is a device array of
- * two doubles accumulated in place.  mu_guess (may be NULL: zero guess) is an
+ * two doubles (three for a 3-D plan) accumulated in place.  mu_guess (may be NULL: zero guess) is an
  * initial guess for mu and receives mu on exit when not NULL.
  * lam_prev must not alias lam_cur.  Errors: as rsfde_step. */
 int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cur,

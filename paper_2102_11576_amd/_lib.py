@@ -86,6 +86,7 @@ def _load():
                                  C.c_double, C.c_double, C.c_double, C.c_double, P, C.c_double,
                                  C.c_double, C.c_int32, P]
     lib.rsfde_set_coeffs.argtypes = [P, C.c_double, C.c_double]
+    lib.rsfde_set_coeffs3.argtypes = [P, C.c_double, C.c_double, C.c_double]
     lib.rsfde_matvec.argtypes = [P, P, P, P]
     lib.rsfde_matvec_noalloc.argtypes = [C.POINTER(rsfde_grid), C.c_double, C.c_double, C.c_double,
                                          C.c_double, P, C.c_double, C.c_double, P, P, P]
@@ -116,7 +117,7 @@ def _load():
     lib.rsfde_destroy.argtypes = [P]
     lib.rsfde_strerror.argtypes = [C.c_int]
     lib.rsfde_strerror.restype = C.c_char_p
-    for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_matvec",
+    for f in ("rsfde_setup", "rsfde_setup3", "rsfde_set_coeffs", "rsfde_set_coeffs3", "rsfde_matvec",
               "rsfde_matvec_noalloc", "rsfde_precond_apply",
               "rsfde_step", "rsfde_step_src", "rsfde_solve", "rsfde_march_ensemble", "rsfde_adjoint_step", "rsfde_destroy",
               "rsfde_profile", "rsfde_profile_read", "rsfde_batch_setup", "rsfde_batch_set_coeffs",
@@ -223,6 +224,10 @@ def rsfde_setup3(n, box, alphas, ks, mask, eta, dt, max_restart=30, stream=None)
 
 def rsfde_set_coeffs(plan, kx, ky):
     _raise(_lib.rsfde_set_coeffs(plan, float(kx), float(ky)), "rsfde_set_coeffs")
+
+
+def rsfde_set_coeffs3(plan, kx, ky, kz):
+    _raise(_lib.rsfde_set_coeffs3(plan, float(kx), float(ky), float(kz)), "rsfde_set_coeffs3")
 
 
 def rsfde_matvec(plan, x, y, stream=None):

@@ -1,4 +1,5 @@
-"""Differentiable time march: u(T) as a function of (u0, kx, ky).
+"""Differentiable time march: u(T) as a function of (u0, kx, ky) (and kz on a
+three-dimensional plan).
 
 Forward: m implicit steps through rsfde_step, keeping checkpoints every s
 steps (s = ceil(sqrt(m)) by default).  Backward: for each checkpoint segment
@@ -10,6 +11,7 @@ and holds device buffers.
 The adjoint of one step M u^k = u^{k-1} + dt mask f(u^{k-1}) (M symmetric):
   mu^k = M^{-1} lam^k,  lam^{k-1} = mu^k + dt mask f'(u^{k-1}) mu^k,
   dL/dkx += <mu^k, (I (x) A_x/kx) u^k>,  dL/dky += <mu^k, (A_y/ky (x) I) u^k>,
+  (3-D: dL/dkz += <mu^k, (A_z/kz (x) I (x) I) u^k>)
 with lam^m = dL/du^m and dL/du0 = lam^0.
 """
 
@@ -37,6 +39,54 @@ def checkpoint_schedule(m: int, every: int = 0) -> List[Tuple[int, int]]:
     return segs
 
 
+def _march_forward(ctx, u0, ks, plan, m, f_kind, opts, every, adj_opts):
+    opts = make_opts() if opts is None else opts
+    kf = tuple(float(k) for k in ks)
+    plan.set_coeffs(*kf)
+    segs = checkpoint_schedule(m, every)
+    u0c = u0.detach().contiguous()
+    ckpt = {0: (u0c.clone(), None)}
+    prev, cur = None, u0c.clone()
+    iters = []
+    for k in range(1, m + 1):
+        nxt, st = plan.step(cur, prev, f_kind, opts)
+        iters.append(st.iters)
+        prev, cur = cur, nxt
+        if any(k == a for a, _ in segs):
+            ckpt[k] = (cur.clone(), prev.clone())
+    ctx.plan, ctx.m, ctx.f_kind = plan, m, f_kind
+    ctx.opts = opts
+    ctx.adj_opts = opts if adj_opts is None else adj_opts
+    ctx.segs, ctx.ckpt, ctx.k = segs, ckpt, kf
+    ctx.k_is_tensor = tuple(isinstance(k, torch.Tensor) for k in ks)
+    ctx.forward_iters = iters
+    return cur
+
+
+def _march_backward(ctx, grad_out):
+    """Reverse sweep over the checkpoint segments; returns (dL/du0, dL/dk...)."""
+    plan, f_kind = ctx.plan, ctx.f_kind
+    plan.set_coeffs(*ctx.k)
+    lam = grad_out.detach().contiguous().clone()
+    lam_prev = torch.empty_like(lam)
+    mu = torch.zeros_like(lam)  # previous mu: initial guess of the next adjoint solve
+    dk = torch.zeros(len(ctx.k), dtype=torch.float64, device=lam.device)
+    for (a, b) in reversed(ctx.segs):
+        ua, ua_prev = ctx.ckpt[a]
+        states = [ua]
+        prev, cur = ua_prev, ua
+        for _ in range(a + 1, b + 1):
+            nxt, _ = plan.step(cur, prev, f_kind, ctx.opts)
+            prev, cur = cur, nxt
+            states.append(cur)
+        for k in range(b, a, -1):
+            plan.adjoint_step(states[k - a - 1], states[k - a], lam, f_kind, ctx.adj_opts,
+                              lam_prev, dk, mu)
+            lam, lam_prev = lam_prev, lam
+    grads = tuple(dk[i].clone() if t else None for i, t in enumerate(ctx.k_is_tensor))
+    return (lam,) + grads
+
+
 class RsfdeMarch(torch.autograd.Function):
     """u_T = RsfdeMarch.apply(u0, kx, ky, plan, m, f_kind, opts, every, adj_opts)
 
@@ -47,54 +97,33 @@ class RsfdeMarch(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, kx, ky, plan, m, f_kind, opts=None, every=0, adj_opts=None):
-        opts = make_opts() if opts is None else opts
-        kxf, kyf = float(kx), float(ky)
-        plan.set_coeffs(kxf, kyf)
-        segs = checkpoint_schedule(m, every)
-        u0c = u0.detach().contiguous()
-        ckpt = {0: (u0c.clone(), None)}
-        prev, cur = None, u0c.clone()
-        iters = []
-        for k in range(1, m + 1):
-            nxt, st = plan.step(cur, prev, f_kind, opts)
-            iters.append(st.iters)
-            prev, cur = cur, nxt
-            if any(k == a for a, _ in segs):
-                ckpt[k] = (cur.clone(), prev.clone())
-        ctx.plan, ctx.m, ctx.f_kind = plan, m, f_kind
-        ctx.opts = opts
-        ctx.adj_opts = opts if adj_opts is None else adj_opts
-        ctx.segs, ctx.ckpt, ctx.k = segs, ckpt, (kxf, kyf)
-        ctx.kx_is_tensor = isinstance(kx, torch.Tensor)
-        ctx.ky_is_tensor = isinstance(ky, torch.Tensor)
-        ctx.forward_iters = iters
-        return cur
+        return _march_forward(ctx, u0, (kx, ky), plan, m, f_kind, opts, every, adj_opts)
 
     @staticmethod
     def backward(ctx, grad_out):
-        plan, f_kind = ctx.plan, ctx.f_kind
-        plan.set_coeffs(*ctx.k)
-        lam = grad_out.detach().contiguous().clone()
-        lam_prev = torch.empty_like(lam)
-        mu = torch.zeros_like(lam)  # previous mu: initial guess of the next adjoint solve
-        dk = torch.zeros(2, dtype=torch.float64, device=lam.device)
-        for (a, b) in reversed(ctx.segs):
-            ua, ua_prev = ctx.ckpt[a]
-            states = [ua]
-            prev, cur = ua_prev, ua
-            for _ in range(a + 1, b + 1):
-                nxt, _ = plan.step(cur, prev, f_kind, ctx.opts)
-                prev, cur = cur, nxt
-                states.append(cur)
-            for k in range(b, a, -1):
-                plan.adjoint_step(states[k - a - 1], states[k - a], lam, f_kind, ctx.adj_opts,
-                                  lam_prev, dk, mu)
-                lam, lam_prev = lam_prev, lam
-        g_kx = dk[0].clone() if ctx.kx_is_tensor else None
-        g_ky = dk[1].clone() if ctx.ky_is_tensor else None
-        return lam, g_kx, g_ky, None, None, None, None, None, None
+        return _march_backward(ctx, grad_out) + (None,) * 6
+
+
+class RsfdeMarch3(torch.autograd.Function):
+    """u_T = RsfdeMarch3.apply(u0, kx, ky, kz, plan, m, f_kind, opts, every,
+    adj_opts) on a three-dimensional plan; gradients for u0, kx, ky, kz."""
+
+    @staticmethod
+    def forward(ctx, u0, kx, ky, kz, plan, m, f_kind, opts=None, every=0, adj_opts=None):
+        if not plan.is3d:
+            raise ValueError("RsfdeMarch3 needs a three-dimensional plan")
+        return _march_forward(ctx, u0, (kx, ky, kz), plan, m, f_kind, opts, every, adj_opts)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        return _march_backward(ctx, grad_out) + (None,) * 6
 
 
 def march(u0, kx, ky, plan, m, f_kind, opts=None, every=0, adj_opts=None):
     """Functional form of RsfdeMarch."""
     return RsfdeMarch.apply(u0, kx, ky, plan, m, f_kind, opts, every, adj_opts)
+
+
+def march3(u0, kx, ky, kz, plan, m, f_kind, opts=None, every=0, adj_opts=None):
+    """Functional form of RsfdeMarch3."""
+    return RsfdeMarch3.apply(u0, kx, ky, kz, plan, m, f_kind, opts, every, adj_opts)

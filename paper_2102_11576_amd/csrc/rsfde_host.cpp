@@ -73,6 +73,7 @@ struct Plan {
   float* lamz32 = nullptr;
   double* lamc64 = nullptr;  // kx lx(slot) + ky ly(j) for the column j * (n1+1) + slot
   float* lamc32 = nullptr;
+  std::vector<double> lx3, ly3;  // unit-k x (slot order) and y eigenvalues, for new kx, ky
   void* R3 = nullptr;        // preconditioner intermediate (y-transformed)
   double* t3 = nullptr;      // matrix-vector intermediate (after the y pass)
 
@@ -337,6 +338,16 @@ hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
   P->tw64[L] = d;
   P->tw32[L] = f;
   return hipSuccess;
+}
+
+// Section 4.1's x and y eigenvalues of a 3-D plan folded into one value per
+// column of the [n3][(n1+1) n2] view: kx lx(slot) + ky ly(j), column j (n1+1) + slot.
+std::vector<double> fold_xy3(const Plan* P) {
+  const size_t ld = (size_t)P->n1 + 1;
+  std::vector<double> lamc(ld * (size_t)P->n2);
+  for (int j = 0; j < P->n2; ++j)
+    for (size_t c = 0; c < ld; ++c) lamc[(size_t)j * ld + c] = P->kx * P->lx3[c] + P->ky * P->ly3[j];
+  return lamc;
 }
 
 // The y and z passes of the three-dimensional product: t3 = t - ky (A_y along
@@ -1568,11 +1579,9 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
     if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
   // Section 4.1's eigenvalues: x in slot order folded with y into one value per
   // column of the [n3][(n1+1) n2] view (k included), z in position order (unit kz).
-  const std::vector<double> lamx = slot_eigs(tau_eigs(t[0]), P->Ldx);
-  const std::vector<double> ly = tau_eigs(t[1]);
-  std::vector<double> lamc((size_t)(n[0] + 1) * n[1]);
-  for (int j = 0; j < n[1]; ++j)
-    for (int c = 0; c < n[0] + 1; ++c) lamc[(size_t)j * (n[0] + 1) + c] = kx * lamx[c] + ky * ly[j];
+  P->lx3 = slot_eigs(tau_eigs(t[0]), P->Ldx);
+  P->ly3 = tau_eigs(t[1]);
+  const std::vector<double> lamc = fold_xy3(P);
   const std::vector<double> lamz = pos_eigs(tau_eigs(t[2]), P->Ldz);
   const std::vector<float> lamc_f(lamc.begin(), lamc.end()), lamz_f(lamz.begin(), lamz.end());
   if (upload(P, &P->lamc64, lamc, s) != hipSuccess || upload(P, &P->lamc32, lamc_f, s) != hipSuccess ||
@@ -1585,10 +1594,42 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
 
 int rsfde_set_coeffs(rsfde_plan plan, double kx, double ky) {
   if (!plan) return RSFDE_EINVAL;
-  if (plan->p.is3d) return RSFDE_EUNSUPPORTED;
-  if (!(kx >= 0.0) || !(ky >= 0.0) || !std::isfinite(kx) || !std::isfinite(ky)) return RSFDE_EINVAL;
-  plan->p.kx = kx;
-  plan->p.ky = ky;
+  return rsfde_set_coeffs3(plan, kx, ky, plan->p.is3d ? plan->p.kz : 0.0);
+}
+
+int rsfde_set_coeffs3(rsfde_plan plan, double kx, double ky, double kz) {
+  using namespace rsfde;
+  if (!plan) return RSFDE_EINVAL;
+  if (!(kx >= 0.0) || !(ky >= 0.0) || !(kz >= 0.0) || !std::isfinite(kx) || !std::isfinite(ky) ||
+      !std::isfinite(kz))
+    return RSFDE_EINVAL;
+  Plan* P = &plan->p;
+  if (!P->is3d) {
+    if (kz != 0.0) return RSFDE_EINVAL;  // a two-dimensional plan has no z factor
+    P->kx = kx;
+    P->ky = ky;
+    return RSFDE_OK;
+  }
+  P->kz = kz;  // applied at launch
+  if (kx == P->kx && ky == P->ky) return RSFDE_OK;
+  // the folded x/y eigenvalue table carries kx and ky: rebuild it once the
+  // device has finished the work that may read it
+  DeviceGuard g(P->dev);
+  if (!g.ok) return RSFDE_EHIP;
+  const double kx0 = P->kx, ky0 = P->ky;
+  P->kx = kx;
+  P->ky = ky;
+  const std::vector<double> lamc = fold_xy3(P);
+  const std::vector<float> lamc_f(lamc.begin(), lamc.end());
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(P->lamc64, lamc.data(), lamc.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(P->lamc32, lamc_f.data(), lamc_f.size() * sizeof(float), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    P->kx = kx0;  // the table may be half written: the plan keeps its old k
+    P->ky = ky0;
+    return RSFDE_EHIP;
+  }
   return RSFDE_OK;
 }
 
@@ -1665,7 +1706,6 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
     return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   if (f_kind < RSFDE_F_NONE || f_kind > RSFDE_F_DECAY) return finish(stats, RSFDE_EINVAL, 0, 0, 0, 0);
   Plan* P = &plan->p;
-  if (P->is3d) return finish(stats, RSFDE_EUNSUPPORTED, 0, 0, 0, 0);
   int rc = validate_opts(P, opts);
   if (rc) return finish(stats, rc, 0, 0, 0, 0);
   DeviceGuard g(P->dev);
@@ -1680,13 +1720,20 @@ int rsfde_adjoint_step(rsfde_plan plan, const double* u_prev, const double* u_cu
     return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);
   rc = solve_core(P, mu, opts, stats, s);
   if (rc != RSFDE_OK) return rc;
-  // directional derivatives of M with respect to kx and ky, dotted with mu
-  if (launch_mv_rows(P->Lcx, u_cur, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, P->n2, 1.0, 0.0,
+  // directional derivatives of M with respect to kx, ky (and kz), dotted with
+  // mu: the unit-k factors applied along each axis (3-D: y slice by slice on
+  // [n3][n2][n1], z on the [n3][n1 n2] view)
+  const int rows = P->n2 * P->n3, plane = P->n1 * P->n2;
+  if (launch_mv_rows(P->Lcx, u_cur, P->mask, P->t, P->symx, P->tw64[P->Lcx], P->n1, rows, 1.0, 0.0,
                      1, s) != hipSuccess ||
       launch_dot_accum(mu, P->t, P->N, P->rw, 4, dk_dev, s) != hipSuccess ||
       launch_mv_cols(P->Lcy, u_cur, nullptr, P->t, P->symy, P->tw64[P->Lcy], P->n1, P->n2, 1.0, 1,
-                     s) != hipSuccess ||
+                     s, P->n3, (size_t)plane) != hipSuccess ||
       launch_dot_accum(mu, P->t, P->N, P->rw, 5, dk_dev + 1, s) != hipSuccess ||
+      (P->is3d &&
+       (launch_mv_cols(P->Lcz, u_cur, nullptr, P->t, P->symz, P->tw64[P->Lcz], plane, P->n3, 1.0, 1,
+                       s) != hipSuccess ||
+        launch_dot_accum(mu, P->t, P->N, P->rw, 6, dk_dev + 2, s) != hipSuccess)) ||
       launch_adj_lambda(mu, u_prev, P->mask, P->dt, f_kind, lam_prev, P->N, s) != hipSuccess)
     return finish(stats, RSFDE_EHIP, stats ? stats->iters : 0, 0, 0, 0);
   if (hipStreamSynchronize(s) != hipSuccess) return finish(stats, RSFDE_EHIP, 0, 0, 0, 0);

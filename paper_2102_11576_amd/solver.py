@@ -61,6 +61,7 @@ class RsfdePlan:
         self.box = tuple(float(v) for v in box)
         self.alpha1, self.alpha2, self.alpha3 = (float(a) for a in alphas)
         self.kx, self.ky, self.kz = (float(k) for k in ks)
+        self.is3d = True
         self.eta, self.dt = float(eta), float(dt)
         self.device = dev
         with torch.cuda.device(dev):
@@ -74,6 +75,7 @@ class RsfdePlan:
                           w.restart if max_restart is None else max_restart, device)
 
     n3 = 1  # two-dimensional unless set by setup3
+    is3d = False
 
     @property
     def N(self):
@@ -96,8 +98,14 @@ class RsfdePlan:
     def __exit__(self, *a):
         self.close()
 
-    def set_coeffs(self, kx, ky):
-        L.rsfde_set_coeffs(self.handle, kx, ky)
+    def set_coeffs(self, kx, ky, kz=None):
+        """New diffusion coefficients; kz (3-D plans) keeps its value when None."""
+        if kz is None:
+            L.rsfde_set_coeffs(self.handle, kx, ky)
+        else:
+            L.rsfde_set_coeffs3(self.handle, kx, ky, kz)
+            if self.is3d:
+                self.kz = float(kz)
         self.kx, self.ky = float(kx), float(ky)
 
     def empty(self):
@@ -144,7 +152,7 @@ class RsfdePlan:
         for t, nm in ((u_prev, "u_prev"), (u_cur, "u_cur"), (lam_cur, "lam_cur"),
                       (lam_prev, "lam_prev")):
             L._check_vec(t, self.N, nm)
-        L._check_vec(dk, 2, "dk")
+        L._check_vec(dk, 3 if self.is3d else 2, "dk")
         if mu is not None:
             L._check_vec(mu, self.N, "mu")
         st = L.rsfde_adjoint_step(self.handle, u_prev, u_cur, lam_cur, f_kind, opts, lam_prev,

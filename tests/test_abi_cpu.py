@@ -181,3 +181,5 @@ def test_setup3_host_validation_fails_fast(lib):
     assert call(grid=C.byref(rsfde_grid3(15, 7, 30, *box))) == -7
     assert call(grid=C.byref(rsfde_grid3(8191, 7, 7, *box))) == -7
     assert h.value is None
+    lib.rsfde_set_coeffs3.argtypes = [P, C.c_double, C.c_double, C.c_double]
+    assert lib.rsfde_set_coeffs3(None, 1.0, 1.0, 1.0) == -1

@@ -5,12 +5,17 @@ matvec      : |w_gpu - w_ref|_inf <= 1e-13 * ||M||_inf ||z||_inf
 precond FP64: |z_gpu - z_ref|_inf <= 1e-12 * ||z_ref||_inf
 precond FP32: |z_gpu - z_ref|_inf <= 2e-5  * ||z_ref||_inf
 march (FP64): ||u_gpu - u_lu||_inf <= 1e-10 ||u_lu||_inf  (GMRES tol 1e-12)
+adjoint     : gradients in (u0, kx, ky, kz) vs the dense-LU adjoint <= 1e-8
+              relative (solves at tol 1e-12, one-vector and s-step forms)
+set_coeffs3 : bit-equal to a plan set up with the new coefficients
 Full size (255^3, the 3-D workload): the whole matvec and preconditioner
 against the oracle's FFT forms, sampled matvec entries summed directly, and
 the true residual of one GPU step measured by the oracle's operator.
 Shapes mix axis lengths (including 1) so that an operator applied along the
 wrong axis, or a slice stride off by one, cannot pass.
 """
+
+import dataclasses
 
 import numpy as np
 import pytest
@@ -24,6 +29,8 @@ pytestmark = pytest.mark.gpu
 rsfde = pytest.importorskip("paper_2102_11576_amd")
 from paper_2102_11576_amd import RsfdePlan, make_opts  # noqa: E402
 from paper_2102_11576_amd._lib import RsfdeError  # noqa: E402
+from paper_2102_11576_amd.autograd import RsfdeMarch3  # noqa: E402
+from workloads.configs import make_config  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -115,19 +122,118 @@ def test_march3_fp32_preconditioner_and_left_mode():
     assert all(abs(a - b) <= 1 for a, b in zip(itL, it_ref)), (itL, it_ref)
 
 
-def test_3d_plan_rejects_2d_only_features():
+def test_3d_plan_rejects_bf16():
     p = _p3((7, 7, 7))
     with _plan(p) as pl:
-        with pytest.raises(RsfdeError):
-            pl.set_coeffs(1.0, 1.0)
         with pytest.raises(RsfdeError):
             pl.precond(_t(np.ones(p.shape)), precision="bf16")
         u = _t(np.ones(p.shape))
         with pytest.raises(RsfdeError):
             pl.step(u, None, 1, make_opts(30, 100, 1e-8, precision="bf16"))
-        lam, dk = pl.empty(), torch.zeros(2, dtype=torch.float64, device=DEV)
+        lam, dk2 = pl.empty(), torch.zeros(2, dtype=torch.float64, device=DEV)
+        with pytest.raises(ValueError):  # a 3-D plan accumulates three k gradients
+            pl.adjoint_step(u, u, u, 1, make_opts(30, 100, 1e-8), lam, dk2)
+
+
+@pytest.mark.parametrize("shape", [(7, 3, 15), (15, 7, 7)], ids=lambda s: "x".join(map(str, s)))
+def test_set_coeffs3_equals_fresh_plan(shape):
+    """New (kx, ky, kz) on an existing plan: the product, both preconditioners
+    and a step are those of a plan set up with them (the same arithmetic, so
+    equal bit for bit), and the oracle with the new k agrees; rsfde_set_coeffs
+    then changes kx, ky and keeps kz."""
+    p = _p3(shape, seed=5)
+    V = np.random.default_rng(9).standard_normal(p.shape)
+    for k in ((0.55, 1.4, 0.3), (1.3, 0.0, 0.3)):
+        q = dataclasses.replace(p, kx=k[0], ky=k[1], kz=k[2])
+        with _plan(p) as pl, _plan(q) as ql:
+            if k[1] == 0.0:
+                pl.set_coeffs(0.2, 0.9, 0.3)
+                pl.set_coeffs(k[0], k[1])  # kz stays 0.3
+            else:
+                pl.set_coeffs(*k)
+            assert torch.equal(pl.matvec(_t(V)), ql.matvec(_t(V)))
+            for prec in ("fp64", "fp32"):
+                assert torch.equal(pl.precond(_t(V), precision=prec), ql.precond(_t(V), precision=prec))
+            o = make_opts(30, 10000, 1e-12)
+            u1, _ = pl.step(_t(V), None, 1, o)
+            u2, _ = ql.step(_t(V), None, 1, o)
+            assert torch.equal(u1, u2)
+            out = pl.matvec(_t(V)).cpu().numpy().reshape(p.shape)
+        assert np.abs(out - O.matvec3(q, V)).max() <= 1e-13 * _norm_M_inf(q) * np.abs(V).max()
+
+
+def test_set_coeffs3_on_2d_plan():
+    w = make_config("c1", n=15, m=2)
+    with RsfdePlan.from_workload(w) as pl:
+        pl.set_coeffs(0.5, 0.7, 0.0)
         with pytest.raises(RsfdeError):
-            pl.adjoint_step(u, u, u, 1, make_opts(30, 100, 1e-8), lam, dk)
+            pl.set_coeffs(0.5, 0.7, 0.1)
+
+
+def _loss_grads_gpu(p, u0, tgt, m, f_kind, opts, every):
+    with _plan(p) as pl:
+        x0 = _t(u0).requires_grad_(True)
+        ks = [torch.tensor(k, dtype=torch.float64, device=DEV, requires_grad=True)
+              for k in (p.kx, p.ky, p.kz)]
+        uT = RsfdeMarch3.apply(x0, *ks, pl, m, f_kind, opts, every)
+        L = ((uT - _t(tgt)) ** 2).sum()
+        L.backward()
+    return (float(L.detach()), x0.grad.cpu().numpy().reshape(p.shape)) + \
+        tuple(float(k.grad) for k in ks)
+
+
+@pytest.mark.parametrize("shape,sstep,every,f_kind",
+                         [((7, 3, 15), 0, 0, 1), ((15, 7, 7), 0, 2, 3), ((3, 15, 7), 0, 1, 2),
+                          ((15, 15, 31), 8, 2, 1)],
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
+def test_adjoint3_matches_oracle(shape, sstep, every, f_kind):
+    """Gradients of ||u^m - u_tgt||^2 w.r.t. (u0, kx, ky, kz) through RsfdeMarch3
+    (HIP forward and adjoint solves, checkpoint segments) against the 3-D
+    oracle's dense-LU adjoint; relative error <= 1e-8 with solves at tol 1e-12.
+    The last case (6975 unknowns) runs the forward and adjoint solves in s-step
+    blocks."""
+    p = dataclasses.replace(_p3(shape, seed=2), kx=0.9, ky=1.1, kz=0.7)
+    rng = np.random.default_rng(sum(shape))
+    u0 = 0.3 * p.mask + 0.2 * rng.standard_normal(p.shape)
+    tgt = 0.1 * rng.standard_normal(p.shape)
+    m = 4
+    L_ref, g0_ref, gx_ref, gy_ref, gz_ref = O.loss_and_grads3_lu(p, u0, m, f_kind, tgt)
+    L, g0, gx, gy, gz = _loss_grads_gpu(p, u0, tgt, m, f_kind, make_opts(30, 100000, 1e-12,
+                                                                       sstep=sstep), every)
+    assert L == pytest.approx(L_ref, rel=1e-10)
+    assert np.abs(g0 - g0_ref).max() <= 1e-8 * np.abs(g0_ref).max()
+    for a, b in ((gx, gx_ref), (gy, gy_ref), (gz, gz_ref)):
+        assert a == pytest.approx(b, rel=1e-8)
+
+
+@pytest.mark.parametrize("sstep", [0, 10])
+def test_adjoint3_fd_check(sstep):
+    """63 x 31 x 31 (60543 unknowns, beyond the dense oracle): the adjoint's
+    directional derivative on 4 seeded directions in (u0, kx, ky, kz) against
+    central differences of two GPU marches (h = 1e-6, solves at tol 1e-12:
+    FD noise about tol / h), relative agreement <= 1e-5."""
+    p = dataclasses.replace(_p3((63, 31, 31), seed=4), kx=1.05, ky=0.85, kz=0.95)
+    rng = np.random.default_rng(21)
+    u0 = 0.3 * p.mask + 0.2 * rng.standard_normal(p.shape)
+    tgt = 0.1 * rng.standard_normal(p.shape)
+    m, f_kind = 4, 1
+    opts = make_opts(30, 100000, 1e-12, sstep=sstep)
+    _, g0, gx, gy, gz = _loss_grads_gpu(p, u0, tgt, m, f_kind, opts, 2)
+
+    def loss(q, v0):
+        with _plan(q) as pl:
+            u, _, _ = pl.march(_t(v0), m, f_kind, opts)
+        return float(((u - _t(tgt)) ** 2).sum())
+
+    h = 1e-6
+    for i in range(4):
+        d = rng.standard_normal(4)
+        du = rng.standard_normal(p.shape) if i % 2 == 0 else np.zeros(p.shape)
+        qp = dataclasses.replace(p, kx=p.kx + h * d[0], ky=p.ky + h * d[1], kz=p.kz + h * d[2])
+        qm = dataclasses.replace(p, kx=p.kx - h * d[0], ky=p.ky - h * d[1], kz=p.kz - h * d[2])
+        fd = (loss(qp, u0 + h * d[3] * du) - loss(qm, u0 - h * d[3] * du)) / (2 * h)
+        an = gx * d[0] + gy * d[1] + gz * d[2] + d[3] * float(np.sum(g0 * du))
+        assert an == pytest.approx(fd, rel=1e-5), (i, an, fd)
 
 
 # ----------------------------- full size: 255^3 -----------------------------
