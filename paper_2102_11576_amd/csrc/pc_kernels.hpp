@@ -34,15 +34,17 @@ namespace rsfde {
 // Row-segment layout of the interleaved (P1, P2) pairs: segments of
 // W = 64 / sizeof(T) slots per row (one 128-byte line of pairs), the
 // segments of one W-slot strip stored row after row, strip after strip.
-// Within every group of 4 slots the order is 0, 2, 1, 3: pass B's two column
-// pairs of a block finish slots (0, 2) in one sweep and (1, 3) in the other,
-// and each sweep then writes whole 32-byte sectors.  Returns the element of
-// P1 (P2 follows it); the array holds 2 W ceil(slots / W) rows values.
+// Within a segment the even slots fill the first half of the line and the odd
+// slots the second: pass B finishes the even slot of each column pair in its
+// first inverse sweep and the odd one in its second, so the blocks of one
+// strip complete a whole 64-byte half-line per sweep (a line written in two
+// halves at two times then leaves the L2 as two full halves).  Returns the
+// element of P1 (P2 follows it); the array holds 2 W ceil(slots / W) rows values.
 template <typename T>
 __device__ __forceinline__ size_t pair_index(int r, int c, int rows) {
   constexpr int W = 64 / (int)sizeof(T);
   const int q = c % W;
-  const int pos = (q & ~3) | ((q & 1) << 1) | ((q >> 1) & 1);
+  const int pos = (q & 1) * (W / 2) + (q >> 1);
   return (((size_t)(c / W) * rows + r) * W + pos) * 2;
 }
 
