@@ -88,6 +88,28 @@ def test_step_residual_full_2047(c3, precision):
     assert 50 < st.iters < 400
 
 
+def test_bf16_preconditioner_not_supported_at_2047_stiffness(c3):
+    """The BF16 (MFMA) preconditioner is not supported at the 2047^2 workload's
+    stiffness, and the library says so instead of returning a wrong answer:
+    the first two steps converge (about 235 inner iterations each), then
+    flexible GMRES stalls (each preconditioned vector's BF16 rounding, about
+    6e-3 relative, is amplified by ||M|| ~ 1e5 in the next product: step 3 took
+    920 iterations when measured) and a step fails with ENOTCONV at an
+    iteration cap of about eleven times the FP64 count per step (109)."""
+    from paper_2102_11576_amd._lib import RSFDE_ENOTCONV, RsfdeError
+    w, p, pl = c3
+    opts = make_opts(w.restart, 1200, w.tol, precision="bf16", sstep=0)
+    u_prev, u = None, _t(w.u0)
+    done = []
+    with pytest.raises(RsfdeError) as ei:
+        for _ in range(6):
+            nxt, st = pl.step(u, u_prev, w.f_kind, opts)
+            done.append(st.iters)
+            u_prev, u = u, nxt
+    assert ei.value.code == RSFDE_ENOTCONV, ei.value
+    assert len(done) >= 2 and all(i < 600 for i in done[:2]), done
+
+
 def test_full_4095_matvec_samples_precond_and_step():
     w = make_config("c5")
     p = O.problem_from_workload(w)
