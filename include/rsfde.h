@@ -148,8 +148,10 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
  *              + (1 - mask) (S (x) S (x) S)((1 + dt/eta) I - Lx - Ly - Lz)^{-1}(S (x) S (x) S)
  * with A_z = c_z G^(alpha3), c_z = dt kz c_alpha3 / h_z^alpha3, and the tau
  * eigenvalues along each axis.  Vectors and the mask are [n3][n2][n1] (x
- * fastest), N = n1 n2 n3.  n1+1, n2+1 and n3+1 must be powers of two (each
- * n <= 4095; EUNSUPPORTED otherwise) and (n1+1) n2 n3 < 2^31.
+ * fastest), N = n1 n2 n3.  Each n <= 4095 (EUNSUPPORTED otherwise) and
+ * (n1+1) n2 n3 < 2^31.  When n1+1, n2+1 and n3+1 are all powers of two the
+ * sine transforms are odd-extension FFTs; otherwise every axis takes the chirp
+ * (Bluestein) form of the DST-I, as rsfde_setup does for other n.
  * rsfde_matvec, rsfde_precond_apply (FP64 / FP32), rsfde_step, rsfde_step_src,
  * rsfde_solve, rsfde_march_ensemble, rsfde_set_coeffs / rsfde_set_coeffs3 and
  * rsfde_adjoint_step (three k gradients) accept a 3-D plan; the BF16

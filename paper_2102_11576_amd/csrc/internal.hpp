@@ -173,6 +173,13 @@ template <typename T>
 hipError_t launch_cd_rows_inv(int L, const T* Y1, const T* Y2, const uint8_t* mask, double* z,
                               const void* chn, const void* khat, const void* tw, int n1, int n2,
                               hipStream_t s);
+// Three-dimensional plans: out = S in along the rows of `batch` slices of
+// [rows][ncol] T values (slice b at offset b * bstride, the columns c < ncol);
+// inB / outB (both or neither): a second array in the same launch.
+template <typename T>
+hipError_t launch_cd_dst_cols(int L, const T* inA, T* outA, const T* inB, T* outB, const void* chn,
+                              const void* khat, const void* tw, int ncol, int rows, int batch,
+                              size_t bstride, hipStream_t s);
 
 // BF16 / MFMA form of the same preconditioner (dense sine-transform GEMMs,
 // any n; dimensions padded to multiples of 128).  A1T holds 2 n1p n2p values

@@ -177,6 +177,40 @@ __global__ __launch_bounds__(CdCfg<L>::THR_R) void k_cd_rows_inv(
   });
 }
 
+// Columns without scaling (the three-dimensional plans' y transforms): out =
+// S_y in for the columns c < ncol of `batch` slices [rows][ncol], slice b at
+// offset b * bstride; with inB given, grid dimension z = 1 transforms inB into
+// outB in the same launch.  in and out must not overlap.
+template <typename T, int L>
+__global__ __launch_bounds__(CdCfg<L>::THR_C) void k_cd_dst_cols(
+    const T* __restrict__ inA, T* __restrict__ outA, const T* __restrict__ inB,
+    T* __restrict__ outB, const cpx<T>* __restrict__ chn, const cpx<T>* __restrict__ khat,
+    const cpx<T>* __restrict__ tw, int ncol, int rows, size_t bstride) {
+  using C = CdCfg<L>;
+  using F = typename C::F;
+  __shared__ T lds[C::BC * lds_len(L)];
+  const size_t off = (size_t)blockIdx.y * bstride;
+  const T* in = (blockIdx.z ? inB : inA) + off;
+  T* out = (blockIdx.z ? outB : outA) + off;
+  const int b = threadIdx.x % C::BC, tau = threadIdx.x / C::BC;
+  const int c = xcd_remap(blockIdx.x, gridDim.x) * C::BC + b;
+  const bool vc = c < ncol;
+  T* my = lds + b;  // regions interleaved (stride BC)
+  cpx<T> reg[F::PP];
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    reg[e].re = (vc && p < rows) ? in[(size_t)p * ncol + c] : T(0);
+    reg[e].im = T(0);
+  });
+  chirp_dst<T, F, C::BC>(reg, tau, chn, khat, tw, my, rows);
+  static_for<F::PP>([&](auto ee) {
+    constexpr int e = decltype(ee)::value;
+    const int p = F::pos(0, tau, e);
+    if (vc && p < rows) out[(size_t)p * ncol + c] = reg[e].re;
+  });
+}
+
 #define RSFDE_CD_CASES(X) \
   X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
 
@@ -211,6 +245,29 @@ hipError_t launch_cd_cols(int L, const T* in, T* Y1, T* Y2, const double* lamx,
     hipLaunchKernelGGL((k_cd_cols<T, LL>), dim3(blocks), dim3(C::THR_C), 0, s, in, Y1, Y2, lamx, \
                        lamy, (const cpx<T>*)chn, (const cpx<T>*)khat, (const cpx<T>*)tw, n1, n2, \
                        kx, ky, dpen);                                                          \
+    return hipGetLastError();                                                                  \
+  }
+    RSFDE_CD_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_cd_dst_cols(int L, const T* inA, T* outA, const T* inB, T* outB, const void* chn,
+                              const void* khat, const void* tw, int ncol, int rows, int batch,
+                              size_t bstride, hipStream_t s) {
+  if (batch < 1 || batch > 65535 || ncol < 1 || rows < 1 || !inA || !outA || (!inB) != (!outB))
+    return hipErrorInvalidValue;
+  switch (L) {
+#define X(LL)                                                                                  \
+  case LL: {                                                                                   \
+    using C = CdCfg<LL>;                                                                       \
+    const dim3 grid((ncol + C::BC - 1) / C::BC, batch, inB ? 2 : 1);                           \
+    hipLaunchKernelGGL((k_cd_dst_cols<T, LL>), grid, dim3(C::THR_C), 0, s, inA, outA, inB,     \
+                       outB, (const cpx<T>*)chn, (const cpx<T>*)khat, (const cpx<T>*)tw, ncol, \
+                       rows, bstride);                                                         \
     return hipGetLastError();                                                                  \
   }
     RSFDE_CD_CASES(X)

@@ -11,4 +11,7 @@ template hipError_t launch_cd_cols<float>(int, const float*, float*, float*, con
 template hipError_t launch_cd_rows_inv<float>(int, const float*, const float*, const uint8_t*, double*,
                                             const void*, const void*, const void*, int, int,
                                             hipStream_t);
+template hipError_t launch_cd_dst_cols<float>(int, const float*, float*, const float*, float*, const void*,
+                                            const void*, const void*, int, int, int, size_t,
+                                            hipStream_t);
 }  // namespace rsfde

@@ -11,4 +11,7 @@ template hipError_t launch_cd_cols<double>(int, const double*, double*, double*,
 template hipError_t launch_cd_rows_inv<double>(int, const double*, const double*, const uint8_t*, double*,
                                             const void*, const void*, const void*, int, int,
                                             hipStream_t);
+template hipError_t launch_cd_dst_cols<double>(int, const double*, double*, const double*, double*, const void*,
+                                            const void*, const void*, int, int, int, size_t,
+                                            hipStream_t);
 }  // namespace rsfde

@@ -68,12 +68,16 @@ struct Plan {
   int n3 = 1;
   double alpha3 = 0, kz = 0;
   int Lcz = 0, Ldz = 0;
+  int Lgz = 0;               // chirp form (some n + 1 not a power of two): z length
+  void* chz[2] = {nullptr, nullptr};
+  void* khz[2] = {nullptr, nullptr};
   double* symz = nullptr;
   double* lamz64 = nullptr;  // z eigenvalues (unit kz), register-position order of Ldz
   float* lamz32 = nullptr;
   double* lamc64 = nullptr;  // kx lx(slot) + ky ly(j) for the column j * (n1+1) + slot
   float* lamc32 = nullptr;
-  std::vector<double> lx3, ly3;  // unit-k x (slot order) and y eigenvalues, for new kx, ky
+  std::vector<double> lx3, ly3;  // unit-k x (slot order; natural in the chirp form) and y
+                                 // eigenvalues, for new kx, ky
   void* R3 = nullptr;        // preconditioner intermediate (y-transformed)
   double* t3 = nullptr;      // matrix-vector intermediate (after the y pass)
 
@@ -341,9 +345,10 @@ hipError_t ensure_twiddles(Plan* P, int L, hipStream_t s) {
 }
 
 // Section 4.1's x and y eigenvalues of a 3-D plan folded into one value per
-// column of the [n3][(n1+1) n2] view: kx lx(slot) + ky ly(j), column j (n1+1) + slot.
+// column of the [n3][ld n2] view: kx lx(slot) + ky ly(j), column j ld + slot,
+// ld = n1 + 1 slots (odd-extension form) or n1 natural positions (chirp form).
 std::vector<double> fold_xy3(const Plan* P) {
-  const size_t ld = (size_t)P->n1 + 1;
+  const size_t ld = (size_t)P->n1 + (P->Lgx ? 0 : 1);
   std::vector<double> lamc(ld * (size_t)P->n2);
   for (int j = 0; j < P->n2; ++j)
     for (size_t c = 0; c < ld; ++c) lamc[(size_t)j * ld + c] = P->kx * P->lx3[c] + P->ky * P->ly3[j];
@@ -417,6 +422,47 @@ int precond_chirp(Plan* P, const double* r, const double* sig, double* z, int t,
   return RSFDE_OK;
 }
 
+// Three-dimensional P_hat^{-1} in the chirp form (some n + 1 not a power of
+// two), T internals; S is the orthonormal DST-I along an axis, S S = I:
+//   A:  W1 = S_x (sig v)                                 (all n2 n3 rows)
+//   B1: W2 = S_y W1                                      (columns of each z slice)
+//   B2: Y1 = S_z (S_z W2 / E1), Y2 = S_z (S_z W2 / E2)   (columns of the [n3][n1 n2]
+//       view; E1 = 1 - (kx lx + ky ly) - kz lz, E2 = E1 + dt/eta)
+//   B3: W1 = S_y Y1, W2 = S_y Y2                         (per z slice)
+//   C:  z  = S_x W1 where mask = 1, S_x W2 where mask = 0  (all rows)
+template <typename T>
+int precond3_chirp(Plan* P, const double* r, const double* sig, double* z, int t,
+                   std::map<int, void*>& tw, hipStream_t s) {
+  const int n1 = P->n1, n2 = P->n2, n3 = P->n3, rows = n2 * n3, plane = n1 * n2;
+  const double N = (double)P->N, ts = (double)sizeof(T);
+  T *W1 = (T*)P->Q, *W2 = (T*)P->R3, *Y1 = (T*)P->P1, *Y2 = (T*)P->P2;
+  {
+    ProfScope ps(P, s, kCatCdRows, 8.0 * N + ts * N);
+    CK(launch_cd_rows_fwd<T>(P->Lgx, r, sig, W1, P->chx[t], P->khx[t], tw[P->Lgx], n1, rows, s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdCols, 2.0 * ts * N);
+    CK(launch_cd_dst_cols<T>(P->Lgy, W1, W2, nullptr, nullptr, P->chy[t], P->khy[t], tw[P->Lgy], n1,
+                             n2, n3, (size_t)plane, s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdCols, 3.0 * ts * N);
+    CK(launch_cd_cols<T>(P->Lgz, W2, Y1, Y2, P->lamc64, P->lamz64, P->chz[t], P->khz[t],
+                         tw[P->Lgz], plane, n3, 1.0, P->kz, P->dpen, s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdCols, 4.0 * ts * N);
+    CK(launch_cd_dst_cols<T>(P->Lgy, Y1, W1, Y2, W2, P->chy[t], P->khy[t], tw[P->Lgy], n1, n2, n3,
+                             (size_t)plane, s));
+  }
+  {
+    ProfScope ps(P, s, kCatCdRowsInv, 2.0 * ts * N + 9.0 * N);
+    CK(launch_cd_rows_inv<T>(P->Lgx, W1, W2, P->mask, z, P->chx[t], P->khx[t], tw[P->Lgx], n1,
+                             rows, s));
+  }
+  return RSFDE_OK;
+}
+
 // Three-dimensional P_hat^{-1} (n + 1 a power of two on every axis), T internals:
 //   A:  Q  = raw x-sine sums of the rows of sig*v            (all n2*n3 rows)
 //   B1: R  = raw y-sine sums of Q's columns                   (per z slice)
@@ -430,6 +476,11 @@ template <typename T>
 int precond3(Plan* P, const double* r, const double* sig, double* z, std::map<int, void*>& tw,
              const T* lamc, const T* lamz, hipStream_t s, double* w, const double* sub,
              double theta) {
+  if (P->Lgx) {  // chirp form, then the product unfused
+    const int rc = precond3_chirp<T>(P, r, sig, z, sizeof(T) == 8 ? 0 : 1, tw, s);
+    if (rc != RSFDE_OK || !w) return rc;
+    return matvec_impl(P, z, w, s, sub, theta);
+  }
   const int n1 = P->n1, n2 = P->n2, n3 = P->n3, ld = n1 + 1, rows = n2 * n3;
   const size_t plane = (size_t)ld * n2;
   const double Kfac = 8.0 / ((double)(n1 + 1) * (double)(n2 + 1) * (double)(n3 + 1));
@@ -1520,8 +1571,11 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
   if (!(eta > 0.0) || !(dt > 0.0) || !std::isfinite(eta) || !std::isfinite(dt)) return RSFDE_EINVAL;
   if (max_restart <= 0) max_restart = 30;
   if (max_restart > kMaxRestart) return RSFDE_EINVAL;
-  for (int a = 0; a < 3; ++a)
-    if (n[a] > kMaxN || !is_pow2(n[a] + 1)) return RSFDE_EUNSUPPORTED;
+  bool pow2 = true;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] > kMaxN) return RSFDE_EUNSUPPORTED;
+    pow2 = pow2 && is_pow2(n[a] + 1);
+  }
   const size_t N = (size_t)n[0] * (size_t)n[1] * (size_t)n[2];
   const size_t slots = (size_t)(n[0] + 1) * (size_t)n[1] * (size_t)n[2];
   if (slots > (size_t)INT32_MAX) return RSFDE_EUNSUPPORTED;
@@ -1566,23 +1620,48 @@ int rsfde_setup3(rsfde_plan* out, const rsfde_grid3* grid, double alpha1, double
   P->Lcx = std::max(2, next_pow2(2L * n[0]));
   P->Lcy = std::max(2, next_pow2(2L * n[1]));
   P->Lcz = std::max(2, next_pow2(2L * n[2]));
-  P->Ldx = 2 * (n[0] + 1);
-  P->Ldy = 2 * (n[1] + 1);
-  P->Ldz = 2 * (n[2] + 1);
+  if (pow2) {  // odd-extension sine transforms
+    P->Ldx = 2 * (n[0] + 1);
+    P->Ldy = 2 * (n[1] + 1);
+    P->Ldz = 2 * (n[2] + 1);
+  } else {  // chirp form on every axis
+    P->Lgx = std::max(2, next_pow2(2L * n[0] - 1));
+    P->Lgy = std::max(2, next_pow2(2L * n[1] - 1));
+    P->Lgz = std::max(2, next_pow2(2L * n[2] - 1));
+  }
   int rc = alloc_common(P, mask_dev, slots, s);
   if (rc != RSFDE_OK) return fail(rc);
   if (upload(P, &P->symx, conv_symbol_pos(t[0], P->Lcx), s) != hipSuccess ||
       upload(P, &P->symy, conv_symbol_pos(t[1], P->Lcy), s) != hipSuccess ||
       upload(P, &P->symz, conv_symbol_pos(t[2], P->Lcz), s) != hipSuccess)
     return fail(RSFDE_ENOMEM);
-  for (int L : {P->Lcx, P->Lcy, P->Lcz, P->Ldx, P->Ldy, P->Ldz})
+  for (int L : {P->Lcx, P->Lcy, P->Lcz, P->Ldx, P->Ldy, P->Ldz, P->Lgx, P->Lgy, P->Lgz})
     if (ensure_twiddles(P, L, s) != hipSuccess) return fail(RSFDE_ENOMEM);
+  if (!pow2) {  // chirp tables per axis (FP64 and FP32)
+    struct Dir { int n, L; void **ch, **kh; };
+    for (Dir d : {Dir{n[0], P->Lgx, P->chx, P->khx}, Dir{n[1], P->Lgy, P->chy, P->khy},
+                  Dir{n[2], P->Lgz, P->chz, P->khz}}) {
+      std::vector<double> ch, kh;
+      chirp_tables(d.n, d.L, ch, kh);
+      const std::vector<float> chf(ch.begin(), ch.end()), khf(kh.begin(), kh.end());
+      double *a = nullptr, *b = nullptr;
+      float *c = nullptr, *e = nullptr;
+      if (upload(P, &a, ch, s) != hipSuccess || upload(P, &b, kh, s) != hipSuccess ||
+          upload(P, &c, chf, s) != hipSuccess || upload(P, &e, khf, s) != hipSuccess)
+        return fail(RSFDE_ENOMEM);
+      d.ch[0] = a;
+      d.kh[0] = b;
+      d.ch[1] = c;
+      d.kh[1] = e;
+    }
+  }
   // Section 4.1's eigenvalues: x in slot order folded with y into one value per
   // column of the [n3][(n1+1) n2] view (k included), z in position order (unit kz).
-  P->lx3 = slot_eigs(tau_eigs(t[0]), P->Ldx);
+  // (chirp form: natural order on every axis)
+  P->lx3 = pow2 ? slot_eigs(tau_eigs(t[0]), P->Ldx) : tau_eigs(t[0]);
   P->ly3 = tau_eigs(t[1]);
   const std::vector<double> lamc = fold_xy3(P);
-  const std::vector<double> lamz = pos_eigs(tau_eigs(t[2]), P->Ldz);
+  const std::vector<double> lamz = pow2 ? pos_eigs(tau_eigs(t[2]), P->Ldz) : tau_eigs(t[2]);
   const std::vector<float> lamc_f(lamc.begin(), lamc.end()), lamz_f(lamz.begin(), lamz.end());
   if (upload(P, &P->lamc64, lamc, s) != hipSuccess || upload(P, &P->lamc32, lamc_f, s) != hipSuccess ||
       upload(P, &P->lamz64, lamz, s) != hipSuccess || upload(P, &P->lamz32, lamz_f, s) != hipSuccess)

@@ -12,7 +12,8 @@ Full size (255^3, the 3-D workload): the whole matvec and preconditioner
 against the oracle's FFT forms, sampled matvec entries summed directly, and
 the true residual of one GPU step measured by the oracle's operator.
 Shapes mix axis lengths (including 1) so that an operator applied along the
-wrong axis, or a slice stride off by one, cannot pass.
+wrong axis, or a slice stride off by one, cannot pass; shapes with n + 1 not a
+power of two on some axis take the chirp form of the sine transforms.
 """
 
 import dataclasses
@@ -61,7 +62,9 @@ def _norm_M_inf(p):
 
 
 SHAPES = [(1, 1, 1), (3, 1, 7), (7, 3, 1), (1, 7, 3), (7, 7, 7), (15, 7, 3), (3, 15, 31),
-          (31, 31, 31), (63, 15, 7), (15, 63, 31), (127, 31, 15)]
+          (31, 31, 31), (63, 15, 7), (15, 63, 31), (127, 31, 15),
+          # n + 1 not a power of two on some axis: the chirp form on every axis
+          (2, 1, 1), (5, 6, 7), (20, 3, 9), (1, 10, 4), (15, 7, 6), (33, 17, 10), (100, 30, 12)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
@@ -88,6 +91,7 @@ def test_precond3_parity(shape, precision, bar):
 
 
 @pytest.mark.parametrize("shape,sstep", [((7, 7, 7), 0), ((15, 7, 3), 0), ((3, 7, 15), 0),
+                                         ((9, 6, 5), 0), ((20, 17, 13), 8),
                                          ((15, 15, 15), 0), ((15, 15, 31), 0), ((15, 15, 31), 8)],
                          ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else f"s{v}")
 def test_march3_matches_lu(shape, sstep):
@@ -102,8 +106,9 @@ def test_march3_matches_lu(shape, sstep):
     assert all(i > 0 for i in iters)
 
 
-def test_march3_fp32_preconditioner_and_left_mode():
-    w = make_config3d(shape=(15, 7, 31), m=2, seed=3)
+@pytest.mark.parametrize("shape", [(15, 7, 31), (10, 7, 12)], ids=lambda s: "x".join(map(str, s)))
+def test_march3_fp32_preconditioner_and_left_mode(shape):
+    w = make_config3d(shape=shape, m=2, seed=3)
     p = O.problem3_from_workload(w)
     ref = O.march3_lu(p, w.u0, w.m, w.f_kind)
     with RsfdePlan.from_workload3(w) as pl:
@@ -184,6 +189,7 @@ def _loss_grads_gpu(p, u0, tgt, m, f_kind, opts, every):
 
 @pytest.mark.parametrize("shape,sstep,every,f_kind",
                          [((7, 3, 15), 0, 0, 1), ((15, 7, 7), 0, 2, 3), ((3, 15, 7), 0, 1, 2),
+                          ((6, 5, 9), 0, 1, 1),
                           ((15, 15, 31), 8, 2, 1)],
                          ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
 def test_adjoint3_matches_oracle(shape, sstep, every, f_kind):
