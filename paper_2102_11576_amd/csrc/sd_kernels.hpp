@@ -418,7 +418,7 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_inv(
 template <int L>
 struct SdMvCfg {
   using S = Sd<L>;
-  using F = Fft<L, fft_pts(L)>;  // convolution engine
+  using F = Fft<L, sd_conv_pts(L)>;  // convolution engine
   // The two sine transforms of a row pair run one after the other on the
   // first TPD threads (a block is then the convolution's TPF threads, and a
   // block per row pair keeps the whole grid resident at once on 256 CUs).
