@@ -111,6 +111,10 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the c1 / c2 / c5 legs")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--jsonl", default=None,
+                    help="per-step metrics: after the timed runs, one more FP64 march of the "
+                         "workload writes a JSON line per step (iterations, restarts, relative "
+                         "residual, status, ms) to this file, after a header line")
     ap.add_argument("--no-one-vector", action="store_true",
                     help="skip the one-vector-per-step comparison march (profiling runs)")
     ap.add_argument("--sstep", type=int, default=10,
@@ -685,6 +689,14 @@ def main():
         log(f"run {r + 1}: {1e3 * t / K:.2f} ms/step")
     t64 = float(np.median(runs))
     value = w.N * K / t64
+    if args.jsonl:  # outside the timed region
+        with open(args.jsonl, "a") as fh:
+            fh.write(json.dumps({"workload": w.name, "n1": w.n1, "n2": w.n2, "steps": K,
+                                 "precision": "fp64", "sstep": args.sstep, "restart": w.restart,
+                                 "tol": w.tol, "ms_per_step_median": 1e3 * t64 / K}) + "\n")
+            plan.march(u0, K, w.f_kind, make_opts(w.restart, 100000, w.tol, "fp64",
+                                                  sstep=args.sstep), log=fh)
+        log(f"per-step metrics written to {args.jsonl}")
     form = f"s-step (s={args.sstep})" if args.sstep >= 2 else "one vector per step"
     log(f"fp64, {form}: {1e3 * t64 / K:.2f} ms/step (median), {np.mean(it64):.1f} iterations/step")
     out = {

@@ -6,6 +6,8 @@ arithmetic step runs in librsfde's HIP kernels.
 
 from __future__ import annotations
 
+import json
+import time
 from dataclasses import dataclass
 from typing import List, Optional
 
@@ -160,26 +162,47 @@ class RsfdePlan:
         return StepStats(st.iters, st.restarts, st.relres, st.status)
 
     def march(self, u0, m, f_kind, opts, keep: Optional[List[int]] = None, src=None,
-              src_scale=None):
+              src_scale=None, u_prev=None, k0: int = 0, log=None):
         """Run m implicit steps from u0 (flat FP64 tensor).  Returns (u^m, iters per
         step, {k: u^k for k in keep}).  src / src_scale(k): optional source field
-        and its factor at step k (evaluated at t_{k-1})."""
+        and its factor at step k (evaluated at t_{k-1}).
+
+        Resume: a march interrupted after step k0 continues from u0 = u^{k0} and
+        u_prev = u^{k0-1} (the state the extrapolated initial guess 2 u^{k0} -
+        u^{k0-1} needs); step numbers (keep, src_scale, log) are then k0 + 1 ..
+        k0 + m, and the result equals that of the uninterrupted march.
+        log: a path or a text file; one JSON line per step with the step number,
+        inner iterations, restarts, the solver's final relative residual, status
+        and the host wall time of the step call in ms."""
         L._check_vec(u0, self.N, "u0")
-        bufs = [u0.clone(), self.empty(), self.empty()]
-        cur, prev = 0, None
+        if u_prev is not None:
+            L._check_vec(u_prev, self.N, "u_prev")
+        bufs = [u0.clone(), self.empty() if u_prev is None else u_prev.clone(), self.empty()]
+        cur, prev = 0, (None if u_prev is None else 1)
         iters = []
         saved = {}
-        if keep and 0 in keep:
-            saved[0] = u0.clone()
-        for k in range(1, m + 1):
-            nxt = [i for i in range(3) if i != cur and i != prev][0]
-            _, st = self.step(bufs[cur], None if prev is None else bufs[prev], f_kind, opts,
-                              bufs[nxt], src=src,
-                              src_scale=1.0 if src_scale is None else src_scale(k))
-            iters.append(st.iters)
-            prev, cur = cur, nxt
-            if keep and k in keep:
-                saved[k] = bufs[cur].clone()
+        if keep and k0 in keep:
+            saved[k0] = u0.clone()
+        own = isinstance(log, (str, bytes)) or hasattr(log, "__fspath__")
+        fh = open(log, "a") if own else log
+        try:
+            for k in range(k0 + 1, k0 + m + 1):
+                nxt = [i for i in range(3) if i != cur and i != prev][0]
+                t0 = time.perf_counter()
+                _, st = self.step(bufs[cur], None if prev is None else bufs[prev], f_kind, opts,
+                                  bufs[nxt], src=src,
+                                  src_scale=1.0 if src_scale is None else src_scale(k))
+                if fh is not None:
+                    fh.write(json.dumps({"step": k, "iters": st.iters, "restarts": st.restarts,
+                                         "relres": st.relres, "status": st.status,
+                                         "ms": 1e3 * (time.perf_counter() - t0)}) + "\n")
+                iters.append(st.iters)
+                prev, cur = cur, nxt
+                if keep and k in keep:
+                    saved[k] = bufs[cur].clone()
+        finally:
+            if own:
+                fh.close()
         return bufs[cur], iters, saved
 
 
