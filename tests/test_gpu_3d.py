@@ -140,7 +140,8 @@ def test_3d_plan_rejects_bf16():
             pl.adjoint_step(u, u, u, 1, make_opts(30, 100, 1e-8), lam, dk2)
 
 
-@pytest.mark.parametrize("shape", [(7, 3, 15), (15, 7, 7)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", [(7, 3, 15), (15, 7, 7), (6, 5, 9)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_set_coeffs3_equals_fresh_plan(shape):
     """New (kx, ky, kz) on an existing plan: the product, both preconditioners
     and a step are those of a plan set up with them (the same arithmetic, so
