@@ -590,7 +590,8 @@ def log(msg):
 
 def ablations(args):
     """Arnoldi-traffic ablations on the benchmark march (FP64 preconditioner,
-    tol 1e-8): GMRES form (one-vector CGS, CGS2, s-step s = 2..16) and restart
+    tol 1e-8): GMRES form (one-vector CGS, CGS2, s-step s = 2..16, which is also the
+    sweep of s) and restart
     length, each timed over the same steps.  One JSON line."""
     import numpy as np
     import torch
@@ -616,7 +617,7 @@ def ablations(args):
             f"{row['ms_per_step']:.2f} ms/step, {row['gmres_iters_per_step']:.1f} it/step")
         return row
     rows = [run(w.restart, 0, -1), run(w.restart, 0, 1)]
-    rows += [run(w.restart, s) for s in (2, 4, 8, 16)]
+    rows += [run(w.restart, s) for s in (2, 4, 6, 8, 10, 12, 16)]
     rows += [run(r, 8) for r in (10, 20, 40, 60)]
     rows += [run(r, 0, -1) for r in (10, 20, 40, 60)]
     plan.close()
