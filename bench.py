@@ -186,7 +186,7 @@ def cpu_baseline(w, gpu_iters_per_step, log=lambda m: None):
     t_cycle = time.perf_counter() - t0
     log(f"CPU oracle: one GMRES({w.restart}) cycle at {w.n1}^2 in {t_cycle:.1f} s")
     t_step = t_rhs + (gpu_iters_per_step / w.restart) * t_cycle
-    # dense LU on the c1 shape (the survey's O1 tier), whole
+    # dense LU on the 63^2 shape (the oracle's dense tier), whole
     w1 = make_config("c1")
     p1 = O.problem_from_workload(w1)
     t0 = time.perf_counter()
