@@ -182,3 +182,15 @@ def test_setup3_host_validation_fails_fast(lib):
     assert h.value is None
     lib.rsfde_set_coeffs3.argtypes = [P, C.c_double, C.c_double, C.c_double]
     assert lib.rsfde_set_coeffs3(None, 1.0, 1.0, 1.0) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and a
+    message saying so (before touching any device)."""
+    import json
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2, r.stderr[-2000:]
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
