@@ -21,6 +21,10 @@ int stream_blocks(size_t N) {
 
 int red_blocks(size_t N) {
   size_t b = (N + (size_t)kRedThreads * 16 - 1) / ((size_t)kRedThreads * 16);
+  if (b < 16) {  // small vectors: one element pair per thread, up to 16 blocks
+    const size_t m = (N + (size_t)kRedThreads * 2 - 1) / ((size_t)kRedThreads * 2);
+    b = m < 16 ? m : 16;
+  }
   if (b < 1) b = 1;
   if (b > (size_t)kMaxRedBlocks) b = kMaxRedBlocks;
   return (int)b;
