@@ -13,7 +13,8 @@ against the oracle's FFT forms, sampled matvec entries summed directly, and
 the true residual of one GPU step measured by the oracle's operator.
 Shapes mix axis lengths (including 1) so that an operator applied along the
 wrong axis, or a slice stride off by one, cannot pass; shapes with n + 1 not a
-power of two on some axis take the chirp form of the sine transforms.
+power of two on some axis take the chirp form of the sine transforms, and
+shapes with n1 + 1 = 256 run the row passes at the length of the 255^3 workload.
 """
 
 import dataclasses
@@ -64,7 +65,9 @@ def _norm_M_inf(p):
 SHAPES = [(1, 1, 1), (3, 1, 7), (7, 3, 1), (1, 7, 3), (7, 7, 7), (15, 7, 3), (3, 15, 31),
           (31, 31, 31), (63, 15, 7), (15, 63, 31), (127, 31, 15),
           # n + 1 not a power of two on some axis: the chirp form on every axis
-          (2, 1, 1), (5, 6, 7), (20, 3, 9), (1, 10, 4), (15, 7, 6), (33, 17, 10), (100, 30, 12)]
+          (2, 1, 1), (5, 6, 7), (20, 3, 9), (1, 10, 4), (15, 7, 6), (33, 17, 10), (100, 30, 12),
+          # n1 + 1 = 256: the row passes at the 255^3 workload's length (L = 512)
+          (255, 7, 3), (255, 1, 5)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
@@ -92,6 +95,7 @@ def test_precond3_parity(shape, precision, bar):
 
 @pytest.mark.parametrize("shape,sstep", [((7, 7, 7), 0), ((15, 7, 3), 0), ((3, 7, 15), 0),
                                          ((9, 6, 5), 0), ((20, 17, 13), 8),
+                                         ((255, 3, 7), 0), ((255, 3, 7), 8),
                                          ((15, 15, 15), 0), ((15, 15, 31), 0), ((15, 15, 31), 8)],
                          ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else f"s{v}")
 def test_march3_matches_lu(shape, sstep):
