@@ -419,15 +419,22 @@ template <int L>
 struct SdMvCfg {
   using S = Sd<L>;
   using F = Fft<L, sd_conv_pts(L)>;  // convolution engine
-  // The two sine transforms of a row pair run one after the other on the
-  // first TPD threads (a block is then the convolution's TPF threads, and a
-  // block per row pair keeps the whole grid resident at once on 256 CUs).
-  static constexpr int THR = S::TPD > F::TPF ? S::TPD : F::TPF;
-  // LDS in doubles: row a's staged z [0, L/2), then the transform region (type
-  // T), which row b's staged z [L/2, L) replaces; the convolution overlays all.
+  // Up to L = 2048 (grids of at most 1023 rows, too few row pairs to fill the
+  // GPU) the two sine transforms of a row pair run at once, on 2 TPD
+  // threads.  From L = 4096 on they run one after the other on the first TPD
+  // threads (a block is then the convolution's TPF threads, and a block per
+  // row pair keeps the whole grid resident at once on 256 CUs).
+  static constexpr bool CONC = L <= 2048;
+  static constexpr int TD = CONC ? 2 * S::TPD : S::TPD;
+  static constexpr int THR = TD > F::TPF ? TD : F::TPF;
+  // LDS in doubles.  Sequential: row a's staged z [0, L/2), then the transform
+  // region (type T), which row b's staged z [L/2, L) replaces.  Concurrent:
+  // the staged z of both rows [0, L), then the two regions.  The convolution
+  // overlays all.
   template <typename T>
   static constexpr int lds_doubles() {
-    constexpr int a = L / 2 + (S::LEN * (int)sizeof(T) + 7) / 8;
+    constexpr int a = CONC ? L + (2 * S::LEN * (int)sizeof(T) + 7) / 8
+                           : L / 2 + (S::LEN * (int)sizeof(T) + 7) / 8;
     constexpr int b = lds_len(L);
     return a > b ? a : b;
   }
@@ -465,7 +472,24 @@ void k_sd_rows_inv_mv(
   const int ra = 2 * pair, rb = ra + 1;
   const bool va = ra < n2, vb = rb < n2;
   // ---- the inverse sine transforms of rows ra and rb
-  {
+  if constexpr (M::CONC) {  // both at once: row ra + h on threads [h TPD, (h + 1) TPD)
+    const int h = tid >= S::TPD ? 1 : 0;
+    const int th = tid - h * S::TPD;
+    const bool act = tid < 2 * S::TPD;
+    const bool g = act && th < S::NG;
+    const int r = act ? th / S::TS : 0, tau = th % S::TS;
+    const int row = ra + h;
+    const bool vr = row < n2;
+    T* region = reinterpret_cast<T*>(lds + L) + h * S::LEN;
+    cpx<T> reg[16];
+    const cpx<T> w1 = twL[g ? th : 0];
+    Roots<T, typename S::Fs> rs;
+    rs.load_inv(tau, twS);
+    if (act) sd_load_spectrum<T, L>(reg, P, row, vr, r, tau, n2, msl);
+    sd_inverse<T, L, 1, TWs, true>(reg, g, th, r, tau, w1, rs, region, act);
+    if (g) sd_store_z<T, L, ZT>(reg, th, row, vr, n1, mask, z, lds + h * (L / 2));
+    __syncthreads();
+  } else {
     const bool act = tid < S::TPD;
     T* region = reinterpret_cast<T*>(lds + L / 2);
 #pragma unroll 1
