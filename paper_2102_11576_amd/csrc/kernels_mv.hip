@@ -28,7 +28,13 @@ struct MvCfg {
   }
   static constexpr int TPF = F::TPF;
   static constexpr int BR = (256 / TPF) > 0 ? (256 / TPF) : 1;             // FFTs per row block
-  static constexpr int BC = (512 / TPF) > 16 ? 16 : ((512 / TPF) > 0 ? (512 / TPF) : 1);
+  // column pairs per column block: two at L = 1024 and 2048 (two-dimensional
+  // grids of 511 or 1023 columns: more, smaller blocks spread them over more
+  // CUs; the 3-D plans' many-column views keep the larger blocks), 512 / TPF
+  // otherwise
+  static constexpr int BC = (L >= 1024 && L <= 2048)
+                                ? 2
+                                : ((512 / TPF) > 16 ? 16 : ((512 / TPF) > 0 ? (512 / TPF) : 1));
   static constexpr int THR_R = BR * TPF;
   static constexpr int THR_C = BC * TPF;
 };

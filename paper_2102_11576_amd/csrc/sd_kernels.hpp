@@ -4,8 +4,8 @@
 // as the plain passes (Q strip-tiled, the (P1, P2) pairs in pair_index order),
 // but the x slots follow Sd<L>::slot, and pass B's y eigenvalues are indexed
 // by block position.  One transform takes 9 sub-FFTs of TS threads (TPD
-// threads); the row passes run 64 / TS transforms per block and pass B as many
-// column pairs, interleaved, so that a block is 9 full wavefronts.
+// threads); the row passes run ND transforms per block and pass B BC column
+// pairs, interleaved (SdRows, SdCols).
 #pragma once
 
 #include "sd_engine.hpp"
@@ -13,17 +13,19 @@
 namespace rsfde {
 
 // Transforms per block of the row passes and column pairs per block of pass B
-// (one transform = 9 sub-FFTs of TS threads each): one from L = 4096 on, 16 /
-// TS below.  Small blocks keep more of them resident per CU (pass B's pair
-// takes 38 KB of LDS with its stash), which hides more latency.
+// (one transform = 9 sub-FFTs of TS threads each): one from L = 4096 on and
+// up to L = 1024 (grids of at most 511 rows or columns: more, smaller blocks
+// spread them over more CUs), 16 / TS = 2 at L = 2048.  Small blocks keep
+// more of them resident per CU (pass B's pair takes 38 KB of LDS with its
+// stash at L = 4096), which hides more latency.
 template <int L>
 struct SdRows {
-  static constexpr int ND = Sd<L>::TS >= 16 ? 1 : 16 / Sd<L>::TS;
+  static constexpr int ND = (L <= 1024 || Sd<L>::TS >= 16) ? 1 : 16 / Sd<L>::TS;
   static constexpr int THR = ND * Sd<L>::TPD;
 };
 template <int L>
 struct SdCols {
-  static constexpr int BC = Sd<L>::TS >= 16 ? 1 : 16 / Sd<L>::TS;
+  static constexpr int BC = (L <= 1024 || Sd<L>::TS >= 16) ? 1 : 16 / Sd<L>::TS;
   static constexpr int THR = BC * Sd<L>::TPD;
 };
 // Threads of one sub-FFT inside one wavefront (ST: LDS interleave of the
