@@ -26,7 +26,10 @@ struct SdRows {
 template <int L>
 struct SdCols {
   static constexpr int BC = (L <= 1024 || Sd<L>::TS >= 16) ? 1 : 16 / Sd<L>::TS;
-  static constexpr int THR = BC * Sd<L>::TPD;
+  // Up to L = 2048 the two inverse sweeps of a column pair run at once, on a
+  // second set of BC TPD threads (too few column pairs to fill the GPU there).
+  static constexpr bool CONC = L <= 2048;
+  static constexpr int THR = (CONC ? 2 : 1) * BC * Sd<L>::TPD;
 };
 // Threads of one sub-FFT inside one wavefront (ST: LDS interleave of the
 // transforms of a block): its exchanges then need no block barrier.
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
   constexpr int TWs = sd_tw<L, BC>();
   using Fs = typename S::Fs;
   using V2 = typename Vec2<T>::type;
-  __shared__ T lds[BC * S::LEN];
+  __shared__ T lds[(SdCols<L>::CONC ? 2 : 1) * BC * S::LEN];
   __shared__ T stash[BC * 16 * S::TPD];  // rho_b between the two inverse sweeps
   {  // member of a batched launch (grid dimension z)
     const size_t mo = mb.off(blockIdx.z);
@@ -281,19 +284,24 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
       ky = (T)mk[mo + 1];
     }
   }
+  constexpr bool CONC = SdCols<L>::CONC;
   const int tid = threadIdx.x;
-  const int b = tid % BC, tg = tid / BC;
+  // set h = 1 (CONC only) takes the second inverse sweep
+  const int h = CONC ? tid / (BC * S::TPD) : 0;
+  const int tl = tid - h * (BC * S::TPD);
+  const int b = tl % BC, tg = tl / BC;
   const int strip = xcd_remap(blockIdx.x, gridDim.x);
   const int ca = 2 * (strip * BC + b), cb = ca + 1;
   const int ld = n1 + 1, hp = (n2 + 1) >> 1;
   const bool va = ca < ld;  // ld even: both columns or neither
+  const bool f0 = h == 0;   // threads of the forward sweep
   const bool g = tg < S::NG;
   const int r = tg / S::TS, tau = tg % S::TS;
   cpx<T> reg[16];
   // the loads of the tables (clamped addresses) go out with the data's
   const cpx<T> w1 = twL[g ? tg : 0];  // the group root of all three sweeps (W_L^p)
   const T lxa = kx * lamx_slot[va ? ca : 0], lxb = kx * lamx_slot[va ? cb : 0];
-  if (g) {  // clamped loads, all in flight at once
+  if (g && f0) {  // clamped loads, all in flight at once
     const int cc = va ? ca : 0;
     static_for<16>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -306,11 +314,11 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
       reg[m].im = sgn * q.y;
     });
   }
-  T* my = lds + b;  // regions interleaved (stride BC)
+  T* my = lds + h * (BC * S::LEN) + b;  // regions interleaved (stride BC); one per set
   {
     Roots<T, Fs> rs;  // (loaded per sweep: held across the kernel they cost occupancy)
     rs.load_fwd(tau, twS);
-    sd_forward<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, rs, my);
+    sd_forward<T, L, BC, TWs, false>(reg, g && f0, tg, r, tau, w1, rs, my, f0);
   }
   // spectrum = 2 rho_b - 2i rho_a; rho_b waits in LDS for the second column
   // (in registers it would cost a wavefront of occupancy)
@@ -323,17 +331,50 @@ __global__ __launch_bounds__(SdCols<L>::THR) __attribute__((amdgpu_waves_per_eu(
     constexpr int e = decltype(ee)::value;
     ly[e] = ky * lamy[Fs::pos(Fs::NS - 1, tau, e)];
   });
-  static_for<16>([&](auto ee) {
-    constexpr int e = decltype(ee)::value;
-    const T rho_a = (T)-0.5 * reg[e].im;
-    rb[e * S::TPD * BC] = (T)0.5 * reg[e].re;
-    const T e1 = (T)1 - lxa - ly[e];
-    const T e2 = e1 + dpen;
-    const T q = halfK * rho_a / (e1 * e2);
-    // (K rho / 2) (1/E2 - i/E1)
-    reg[e].re = q * e1;
-    reg[e].im = -q * e2;
-  });
+  if (f0) {
+    static_for<16>([&](auto ee) {
+      constexpr int e = decltype(ee)::value;
+      const T rho_a = (T)-0.5 * reg[e].im;
+      rb[e * S::TPD * BC] = (T)0.5 * reg[e].re;
+      const T e1 = (T)1 - lxa - ly[e];
+      const T e2 = e1 + dpen;
+      const T q = halfK * rho_a / (e1 * e2);
+      // (K rho / 2) (1/E2 - i/E1)
+      reg[e].re = q * e1;
+      reg[e].im = -q * e2;
+    });
+  }
+  if constexpr (CONC) {
+    // the second set takes rho_b from the stash and runs its sweep beside the first
+    __syncthreads();
+    if (!f0) {
+      static_for<16>([&](auto ee) {
+        constexpr int e = decltype(ee)::value;
+        const T e1 = (T)1 - lxb - ly[e];
+        const T e2 = e1 + dpen;
+        const T q = halfK * rb[e * S::TPD * BC] / (e1 * e2);
+        reg[e].re = q * e1;
+        reg[e].im = -q * e2;
+      });
+    }
+    {
+      Roots<T, Fs> rs;
+      rs.load_inv(tau, twS);
+      sd_inverse<T, L, BC, TWs, false>(reg, g, tg, r, tau, w1, rs, my);
+    }
+    if (g && va) {
+      const int cw = f0 ? ca : cb;
+      static_for<16>([&](auto mm) {
+        constexpr int m = decltype(mm)::value;
+        bool neg;
+        const int j = S::nat(tg, m, neg);
+        if ((m < 8 || (tg != 0 && tg != S::LS / 2)) && j >= 1 && j <= n2)
+          *(V2*)(P + pair_index<T>(j - 1, cw, n2)) =
+              neg ? V2{-reg[m].re, -reg[m].im} : V2{reg[m].re, reg[m].im};
+      });
+    }
+    return;
+  }
   {
     Roots<T, Fs> rs;
     rs.load_inv(tau, twS);
