@@ -32,14 +32,12 @@ struct Members {
   }
 };
 
-// Points per thread of the register-resident FFT of length L.
-constexpr int fft_pts(int L) { return L < 16 ? L : (L >= 8192 ? 8 : 16); }
+// Points per thread of the register-resident FFT of length L (16 at every
+// length: at L = 8192 a transform is then 512 threads, two blocks per CU by
+// their LDS, in four register stages where 8 points per thread take five).
+constexpr int fft_pts(int L) { return L < 16 ? L : 16; }
 // Points per thread in pass B of the power-of-two preconditioner.
 constexpr int pc_cols_pts(int L) { return L < 16 ? L : 16; }
-// Points per thread of the convolution in the symmetric-form fused pass C
-// (16 at every length: at L = 8192 the block is then 512 threads, for the
-// 288 of the two sine transforms, where fft_pts would make it 1024).
-constexpr int sd_conv_pts(int L) { return L < 16 ? L : 16; }
 
 // Values the device writes for the host after each Arnoldi step.  Lives in
 // pinned, device-visible host memory; the host reads it after an event.
@@ -106,10 +104,6 @@ hipError_t launch_mv_cols(int L, const void* z, const double* t, double* out,
 struct SdTabs {
   const void* twS = nullptr;
   const int32_t* msl = nullptr;
-  // the fused pass's convolution symbol in the register order of
-  // sd_conv_pts(L) points per thread, where that differs from fft_pts(L)
-  // (NULL: the caller's sym serves)
-  const double* symc = nullptr;
 };
 
 // Sine-transform preconditioner, three passes; T = float or double internally.

@@ -143,8 +143,16 @@ __global__ __launch_bounds__(kFinishThreads) void k_bgram_finish(const double* _
   for (int p = blockIdx.x * kWaves + (threadIdx.x >> 6); p < nr * s; p += gridDim.x * kWaves) {
     const int r = p / s, c = p % s;
     const double* src = gpart + (size_t)(r * 16 + c) * kGramBlocks;
+    // all loads first (independent addresses), then the fixed-order sum
+    double v[kGramBlocks / 64];
+#pragma unroll
+    for (int q = 0; q < kGramBlocks / 64; ++q) {
+      const int k = lane + 64 * q;
+      v[q] = k < nb ? src[k] : 0.0;
+    }
     double x = 0.0;
-    for (int k = lane; k < nb; k += 64) x += src[k];
+#pragma unroll
+    for (int q = 0; q < kGramBlocks / 64; ++q) x += v[q];
     x = wave_sum(x);
     if (lane == 0) G[r * 16 + c] = x;
   }

@@ -738,7 +738,7 @@ static hipError_t rows_inv_mv_any(const T* P1, const T* P2, const uint8_t* mask,
   if constexpr (L >= kSdMinL) {
     if (tiled && sd.twS)
       return sd_rows_inv_mv_impl<T, L>(P1, mask, z, z32, t, twT, sd.twS, sd.msl, tw64,
-                                       sd.symc ? sd.symc : sym, coef, dpen, sub, theta, n1, n2,
+                                       sym, coef, dpen, sub, theta, n1, n2,
                                        s, mb, mk);
   }
   return tiled ? pc_rows_inv_mv_impl<T, L, true>(P1, P2, mask, z, z32, t, twT, tw64, sym, coef,

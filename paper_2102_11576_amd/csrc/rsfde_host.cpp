@@ -102,7 +102,6 @@ struct Plan {
   // x / y, and the mirror slots of the x transform
   bool sdx = false, sdy = false;
   int32_t* msl = nullptr;
-  double* symxc = nullptr;  // x symbol in the fused pass's order (sd_conv_pts), where it differs
   // chirp-form preconditioner (n + 1 not a power of two)
   double* lamx_n = nullptr;  // tau eigenvalues, natural order, unit k
   double* lamy_n = nullptr;
@@ -528,7 +527,6 @@ SdTabs sd_x(Plan* P) {
   if (P->sdx) {
     t.twS = (sizeof(T) == 8 ? P->tw64 : P->tw32)[P->Ldx / 16];
     t.msl = P->msl;
-    t.symc = P->symxc;
   }
   return t;
 }
@@ -1486,9 +1484,6 @@ int rsfde_setup(rsfde_plan* out, const rsfde_grid* grid, double alpha1, double a
     if (P->sdx) {
       if (!sd_tables(P->Ldx, tau_eigs(tx), &lamx, nullptr, &msl)) return failx(__LINE__, RSFDE_EUNSUPPORTED);
       if (upload(P, &P->msl, msl, s) != hipSuccess || ensure_twiddles(P, P->Ldx / 16, s) != hipSuccess)
-        return failx(__LINE__, RSFDE_ENOMEM);
-      if (P->Ldx == P->Lcx && sd_conv_pts(P->Lcx) != fft_pts(P->Lcx) &&
-          upload(P, &P->symxc, conv_symbol_pos(tx, P->Lcx, sd_conv_pts(P->Lcx)), s) != hipSuccess)
         return failx(__LINE__, RSFDE_ENOMEM);
     } else {
       lamx = slot_eigs(tau_eigs(tx), P->Ldx);

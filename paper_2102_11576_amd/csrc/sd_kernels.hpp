@@ -461,7 +461,7 @@ __global__ __launch_bounds__(SdRows<L>::THR) void k_sd_rows_inv(
 template <int L>
 struct SdMvCfg {
   using S = Sd<L>;
-  using F = Fft<L, sd_conv_pts(L)>;  // convolution engine
+  using F = Fft<L, fft_pts(L)>;  // convolution engine
   // Up to L = 2048 (grids of at most 1023 rows, too few row pairs to fill the
   // GPU) the two sine transforms of a row pair run at once, on 2 TPD
   // threads.  From L = 4096 on they run one after the other on the first TPD

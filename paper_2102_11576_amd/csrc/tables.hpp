@@ -48,8 +48,8 @@ inline std::vector<double> toeplitz_col(double alpha, int n, double c) {
 
 // Symbol of the circulant embedding of length L (L >= 2n - 1) of the symmetric
 // Toeplitz matrix with first column t, divided by L, in the register-position
-// order of the FFT of length L with P points per thread (default fft_pts(L)).
-inline std::vector<double> conv_symbol_pos(const std::vector<double>& t, int L, int P = 0) {
+// order of the FFT of length L with fft_pts(L) points per thread.
+inline std::vector<double> conv_symbol_pos(const std::vector<double>& t, int L) {
   const int n = (int)t.size();
   std::vector<double> ct = cos_table(L), chat(L);
   for (int f = 0; f < L; ++f) {
@@ -57,7 +57,7 @@ inline std::vector<double> conv_symbol_pos(const std::vector<double>& t, int L, 
     for (int j = 1; j < n; ++j) s += 2.0 * t[j] * ct[(int)(((long long)j * f) % L)];
     chat[f] = s;
   }
-  if (P <= 0) P = fft_pts(L);
+  const int P = fft_pts(L);
   std::vector<double> out(L);
   for (int p = 0; p < L; ++p) out[p] = chat[fft_freq(L, P, p)] / (double)L;
   return out;
