@@ -80,14 +80,25 @@ def test_chirp_precond_parity(n1, n2, precision):
 
 def test_chirp_precond_large_and_maximum_size():
     """n = 1000 x 999 (convolution length 2048) and the largest grid, 4096^2
-    (length 8192), against the library DST of the oracle."""
+    (length 8192), against the library DST of the oracle; at 4096^2 also the
+    FP32 internals and the whole matrix-vector product against the oracle's
+    FFT-Toeplitz form."""
     for n1, n2 in ((1000, 999), (4096, 4096)):
         p = _problem(n1, n2)
         V = np.random.default_rng(n1).standard_normal((n2, n1))
         ref = O.precond_apply_fft(p, V)
         with _plan(p, 8) as pl:
             out = pl.precond(_t(V), precision="fp64").cpu().numpy().reshape(n2, n1)
-        assert_precond(out, ref, p, "fp64", f"chirp {n1}x{n2} fp64")
+            assert_precond(out, ref, p, "fp64", f"chirp {n1}x{n2} fp64")
+            if n1 == 4096:
+                out = pl.precond(_t(V), precision="fp32").cpu().numpy().reshape(n2, n1)
+                assert_precond(out, ref, p, "fp32", f"chirp {n1}x{n2} fp32")
+                mv = pl.matvec(_t(V)).cpu().numpy().reshape(n2, n1)
+                tx = np.abs(p.cx * O.toeplitz_first_column(p.alpha1, p.n1)).sum()
+                ty = np.abs(p.cy * O.toeplitz_first_column(p.alpha2, p.n2)).sum()
+                bound = 1e-13 * (1.0 + p.d + 2 * tx + 2 * ty) * np.abs(V).max()
+                err = np.abs(mv - O.matvec_fast(p, V))
+                assert err.max() <= bound, np.unravel_index(err.argmax(), err.shape)
 
 
 def test_nonpow2_step_matches_lu_both_sides():

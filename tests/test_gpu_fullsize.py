@@ -1,8 +1,9 @@
 """GPU parity at the full configuration sizes (1023^2, 2047^2 and 4095^2), in
 the launch configuration bench.py times.
 
-* matvec: whole output against the oracle's FFT-Toeplitz form (2047^2) and
-  sampled entries summed directly from the Toeplitz rows (4095^2);
+* matvec: whole output against the oracle's FFT-Toeplitz form (2047^2 and
+  4095^2) and, at 4095^2, sampled entries summed directly from the Toeplitz
+  rows;
 * preconditioner: whole output against the oracle's library-DST form, entry
   by entry, over the whole grid and separately over the domain (mask = 1) and
   over the penalty region (mask = 0).  The penalty region's values are about
@@ -122,6 +123,10 @@ def test_full_4095_matvec_samples_precond_and_step():
               [tuple(rng.integers(0, w.n1, 2)) for _ in range(28)]
         for (j, i) in idx:
             assert abs(out[j, i] - O.matvec_entry(p, Z, j, i)) <= bound, (j, i)
+        # and the whole field against the oracle's FFT-Toeplitz form (every
+        # row and column of the length-8192 transforms)
+        err = np.abs(out - O.matvec_fast(p, Z))
+        assert err.max() <= bound, np.unravel_index(err.argmax(), err.shape)
         zp = pl.precond(_t(Z), precision="fp32").cpu().numpy().reshape(w.n2, w.n1)
         ref = O.precond_apply_fft(p, Z)
         assert_precond(zp, ref, p, "fp32", "4095^2 fp32")
