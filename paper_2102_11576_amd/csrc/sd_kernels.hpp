@@ -467,6 +467,9 @@ struct SdMvCfg {
   // threads.  From L = 4096 on they run one after the other on the first TPD
   // threads (a block is then the convolution's TPF threads, and a block per
   // row pair keeps the whole grid resident at once on 256 CUs).
+  // (At L = 2048 the two transform regions and the staged z hold the
+  // concurrent form to three waves per SIMD by their LDS, so its occupancy
+  // hint asks for three; the smaller lengths compile the same either way.)
   static constexpr bool CONC = L <= 2048;
   static constexpr int TD = CONC ? 2 * S::TPD : S::TPD;
   static constexpr int THR = TD > F::TPF ? TD : F::TPF;
@@ -490,7 +493,7 @@ struct SdMvCfg {
 };
 
 template <typename T, int L, typename ZT = double>
-__global__ __launch_bounds__(SdMvCfg<L>::THR) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(SdMvCfg<L>::THR) __attribute__((amdgpu_waves_per_eu(SdMvCfg<L>::CONC ? 3 : 4)))
 void k_sd_rows_inv_mv(
     const T* __restrict__ P, const uint8_t* __restrict__ mask, ZT* __restrict__ z,
     double* __restrict__ t, const cpx<T>* __restrict__ twL, const cpx<T>* __restrict__ twS,
