@@ -273,6 +273,7 @@ int main() {
   worst = std::fmax(worst, run_case<2048, 16, double>(11));
   worst = std::fmax(worst, run_case<4096, 16, double>(12));
   worst = std::fmax(worst, run_case<8192, 16, double>(16));
+  worst = std::fmax(worst, run_case<1024, 8, double>(17));
   worst = std::fmax(worst, run_case<128, 4, double>(13));
   worst = std::fmax(worst, run_case<256, 8, float>(14));
   worst = std::fmax(worst, run_case<4096, 16, float>(15));

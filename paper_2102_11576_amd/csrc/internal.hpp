@@ -32,10 +32,12 @@ struct Members {
   }
 };
 
-// Points per thread of the register-resident FFT of length L (16 at every
-// length: at L = 8192 a transform is then 512 threads, two blocks per CU by
-// their LDS, in four register stages where 8 points per thread take five).
-constexpr int fft_pts(int L) { return L < 16 ? L : 16; }
+// Points per thread of the register-resident FFT of length L: 16, except 8 at
+// L = 1024.  At L = 8192, 16 points make a transform 512 threads, two blocks
+// per CU by their LDS, in four register stages where 8 points take five.  At
+// L = 1024 (grids of at most 511 lines, too few blocks to fill the GPU) 8
+// points give each block twice the threads.
+constexpr int fft_pts(int L) { return L < 16 ? L : (L == 1024 ? 8 : 16); }
 // Points per thread in pass B of the power-of-two preconditioner.
 constexpr int pc_cols_pts(int L) { return L < 16 ? L : 16; }
 
